@@ -1,0 +1,59 @@
+"""Pure-Python literal definitions, for tiny inputs only (test infrastructure).
+
+These share no reasoning with ``saoracle.c``: instead of a byte comparator with a separator
+rule, the text is mapped to integers -- the separator closing read i becomes the integer i, any
+other byte v becomes m + v -- and suffixes are compared as Python lists.  That is the ordered
+alphabet of the text written out (Sec. III fragments, Sec. IV suffix array), with no special
+cases left to get wrong.
+"""
+from __future__ import annotations
+
+
+def to_ints(text: bytes):
+    m = text.count(b"$")
+    out = []
+    r = 0
+    for v in text:
+        if v == ord("$"):
+            out.append(r)
+            r += 1
+        else:
+            out.append(m + v)
+    return out
+
+
+def suffix_array(text: bytes):
+    s = to_ints(text)
+    return sorted(range(len(s)), key=lambda p: s[p:])
+
+
+def lcp_array(text: bytes, sa):
+    s = to_ints(text)
+    out = [0] * len(sa)
+    for i in range(1, len(sa)):
+        p, q = sa[i - 1], sa[i]
+        k = 0
+        while p + k < len(s) and q + k < len(s) and s[p + k] == s[q + k]:
+            k += 1
+        out[i] = k
+    return out
+
+
+def reads(text: bytes):
+    return text.split(b"$")[:-1]
+
+
+def overlaps(text: bytes, min_len: int):
+    rs = reads(text)
+    out = []
+    for a, ra in enumerate(rs):
+        for b, rb in enumerate(rs):
+            if a == b:
+                continue
+            best = 0
+            for l in range(min_len, min(len(ra), len(rb)) + 1):
+                if ra[len(ra) - l:] == rb[:l]:
+                    best = l
+            if best:
+                out.append((a, b, best))
+    return out
