@@ -1,0 +1,190 @@
+/*
+ * saasm.h -- C ABI of the MI355X (gfx950) suffix-array / read-overlap library.
+ *
+ * The library builds the suffix array of shotgun fragments laid end to end (each fragment
+ * closed by its own '$' separator), the LCP array beside it, and the longest suffix-prefix
+ * overlap of every ordered pair of fragments, with hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless the name ends in _h (host memory).
+ *  - Memory: the caller allocates every buffer, including the scratch workspace `ws`.  The
+ *    library never allocates device memory inside these calls and never frees caller memory.
+ *    Workspace contents are scratch: nothing is carried from one call to the next.
+ *  - Streams: every call is ordered on `stream`.  Calls that report a count or status to the
+ *    host (sa_build, sa_overlaps, sa_pack, sa_sort_pairs) synchronise `stream` before they
+ *    return; sa_lcp does not.
+ *  - Errors: every call returns an int status (SA_OK or a negative SA_ERR_*) and never throws
+ *    across the ABI.  sa_last_error() returns a message for the calling thread's last failure.
+ *    On error the outputs are unspecified; inputs are never modified.
+ *  - Thread safety: calls are re-entrant as long as concurrent calls use different workspaces.
+ *  - Text: bytes 'A','C','G','T' and '$'; text[n-1] must be '$'.  Read i is the bytes between
+ *    the (i-1)-th and i-th separator (empty reads, "$$", are allowed).  Positions are offsets
+ *    in the text, separators included; read ids count separators from 0.
+ *  - Size: 1 <= n < 2^30.
+ *
+ * Ordering (Sec. IV of the paper: the suffix array is the sorted array of all suffixes of the
+ * text; Sec. III: the text is the set of shotgun fragments): the separator closing read i
+ * sorts below the one closing read j when i < j, every separator sorts below every base, and
+ * A < C < G < T.  With distinct separators all suffixes differ, so the suffix array is unique.
+ */
+#ifndef SAASM_H
+#define SAASM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SA_OK = 0,
+    SA_PENDING = 1,          /* asynchronous work not finished yet */
+    SA_ERR_INVALID = -1,     /* bad argument: NULL pointer, text not ending in '$', bad tuning */
+    SA_ERR_ALPHABET = -2,    /* a byte other than A, C, G, T, '$' */
+    SA_ERR_TOO_LARGE = -3,   /* n >= 2^30 */
+    SA_ERR_NOMEM = -4,       /* workspace too small (the required size is reported) */
+    SA_ERR_CAPACITY = -5,    /* output buffer too small (the required count is reported) */
+    SA_ERR_HIP = -6,         /* a HIP runtime call or a kernel's own consistency check failed */
+    SA_ERR_NOTFOUND = -7     /* unknown job id or timing key */
+};
+
+/* Launch tuning of the radix sort; a zero field means "use the default".
+ *   digit_bits       4, 8 or 11 bits per LSD pass
+ *   block_threads    256 or 512 threads per workgroup (4 or 8 wave64 wavefronts)
+ *   items_per_thread 8 or 16 keys per thread (tile = block_threads * items_per_thread)
+ *   seg_pack         reserved for the batched path; must be 0 here                          */
+typedef struct {
+    int32_t digit_bits;
+    int32_t block_threads;
+    int32_t items_per_thread;
+    int32_t seg_pack;
+} sa_tuning;
+
+/* Library version string (static storage). */
+const char *sa_version(void);
+
+/* Message describing the calling thread's most recent error (static per-thread storage). */
+const char *sa_last_error(void);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Validation and 2-bit packing.  Sec. III: DNA is a string over the four bases A, C, G, T;    */
+/* the fragments are laid end to end, each followed by its separator.                         */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Words of packed output for a text of n bytes (each array is padded for over-reads). */
+int64_t sa_packed_words(int64_t n);   /* uint32 words of 2-bit codes, 16 bases per word       */
+int64_t sa_sepmask_words(int64_t n);  /* uint32 words of separator bits, 32 positions per word */
+
+/* Workspace bytes for sa_pack. */
+int64_t sa_pack_ws_bytes(int64_t n);
+
+/* sa_pack: validate the text and pack it.
+ *   text      [n] bytes
+ *   packed    [sa_packed_words(n)] out: base j of word w is position 16w+j, stored in bits
+ *             (31-2j, 30-2j), A=0 C=1 G=2 T=3; a separator packs as 0; padding is 0
+ *   sepmask   [sa_sepmask_words(n)] out: bit (31-j) of word w is set when position 32w+j is '$'
+ *   read_end  [cap_reads] out, may be NULL: position of the separator closing each read
+ *   m_h       host out: number of reads (separators)
+ * Returns SA_ERR_ALPHABET / SA_ERR_INVALID for a bad text, SA_ERR_CAPACITY (with *m_h set) when
+ * read_end is given and cap_reads < m.  Synchronises the stream. */
+int sa_pack(const uint8_t *text, int64_t n, uint32_t *packed, uint32_t *sepmask,
+            int32_t *read_end, int64_t cap_reads, int64_t *m_h, void *ws, int64_t ws_bytes,
+            hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Radix sort (Sec. IV: LSD radix sort, each pass a counting sort in which an element's output */
+/* index is the number of elements in lower buckets plus those already in its own bucket;      */
+/* per pass: per-tile digit counts, a prefix sum over the (digit x tile) table, and a scatter).*/
+/* ---------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for sa_sort_pairs on n pairs. */
+int64_t sa_sort_ws_bytes(int64_t n, const sa_tuning *tune_or_null);
+
+/* sa_sort_pairs: stable sort of (key, value) pairs by bits [bit_lo, bit_hi) of the key.
+ *   keys, vals  [n] in/out: sorted in place (the library copies back when the result ends up
+ *               in its workspace)
+ *   0 <= bit_lo < bit_hi <= 64.  Equal digits keep their input order (stability), so bits
+ *   outside the range keep the order they had.  Synchronises the stream. */
+int sa_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
+                  void *ws, int64_t ws_bytes, const sa_tuning *tune_or_null, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Suffix array (Sec. IV), by prefix doubling over LSD radix sorts of rank-pair keys.          */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for sa_build on a text of n bytes. */
+int64_t sa_build_ws_bytes(int64_t n, const sa_tuning *tune_or_null);
+
+/* sa_build: suffix array of the text.
+ *   text         [n] bytes (see conventions)
+ *   sa           [n] out: the permutation of 0..n-1 listing suffixes in sorted order
+ *   isa_or_null  [n] optional out: inverse permutation, isa[sa[i]] == i
+ *   rounds_h     optional host out: number of sort rounds run (first sort + doubling rounds)
+ * Synchronises the stream once per round. */
+int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
+             void *ws, int64_t ws_bytes, const sa_tuning *tune_or_null, int32_t *rounds_h,
+             hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* LCP array beside the suffix array (Kasai's permuted-LCP scan; the paper uses the array for  */
+/* prefix matching between fragments, Sec. IV).                                              */
+/* ---------------------------------------------------------------------------------------- */
+
+int64_t sa_lcp_ws_bytes(int64_t n);
+
+/* sa_lcp: lcp[0] = 0 and lcp[i] = length of the common prefix of the suffixes at sa[i-1] and
+ * sa[i]; separators never match.  sa and isa must come from sa_build on the same text
+ * (isa[sa[i]] == i).  Does not synchronise. */
+int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
+           int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream);
+
+/* Positions scanned per thread by sa_lcp (each thread restarts Kasai's carried bound at its
+ * first position; any value gives the same result).  Process-wide; default 16. */
+int sa_lcp_set_chunk(int32_t chunk);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Suffix-prefix overlaps between fragments (Sec. III: a fragment is 'fir' when it is a prefix */
+/* of another; the weighted overlap graph's edge weights are overlap lengths; Sec. IV: the     */
+/* suffix array answers these prefix tests).                                                  */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for sa_overlaps on a text of n bytes when the walks find `candidates`
+ * suffix/prefix matches (0 gives the size of the fixed part). */
+int64_t sa_overlaps_ws_bytes(int64_t n, int64_t candidates);
+
+/* sa_overlaps: for every ordered pair of distinct reads (a, b), the largest l with
+ * min_len <= l <= min(|a|, |b|) such that the last l bases of a equal the first l bases of b.
+ *   sa, isa, lcp  from sa_build / sa_lcp on the same text
+ *   out           [cap][3] int32 out: rows (a, b, l) sorted by (a, b), one per pair
+ *   n_out_h       host out: number of rows
+ *   ws_needed_h   host out, may be NULL: workspace bytes this text needs
+ * Returns SA_ERR_NOMEM (with *ws_needed_h set) when ws_bytes is too small -- call again with a
+ * larger workspace -- and SA_ERR_CAPACITY (with *n_out_h set) when cap < rows.
+ * Synchronises the stream. */
+int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
+                const int32_t *lcp, int32_t min_len, int32_t *out, int64_t cap,
+                int64_t *n_out_h, void *ws, int64_t ws_bytes, int64_t *ws_needed_h,
+                hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Measurement support.                                                                      */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Per-kernel timing with HIP events recorded on the launch stream around every instrumented
+ * launch.  Keys: "radix_pass", "keybuild", "rank_update", "kasai", "overlap_walk", "pack".
+ * sa_timing_get returns launches, summed duration (ms) and summed algorithmic bytes (the
+ * bytes each launch must move at minimum, as documented per kernel). */
+int sa_timing_enable(int32_t on);
+int sa_timing_reset(void);
+int sa_timing_get(const char *key, int64_t *launches_h, double *total_ms_h, double *bytes_h);
+
+/* sa_copy_u32: plain device copy of n words (dst[i] = src[i]); a reference kernel of known
+ * traffic for calibrating hardware byte counters.  Does not synchronise. */
+int sa_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAASM_H */

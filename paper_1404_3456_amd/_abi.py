@@ -1,0 +1,285 @@
+"""ctypes marshalling for libsaasm.so (see include/saasm.h for every argument's meaning)."""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(HERE, "libsaasm.so")
+
+SA_OK = 0
+SA_PENDING = 1
+SA_ERR_INVALID = -1
+SA_ERR_ALPHABET = -2
+SA_ERR_TOO_LARGE = -3
+SA_ERR_NOMEM = -4
+SA_ERR_CAPACITY = -5
+SA_ERR_HIP = -6
+SA_ERR_NOTFOUND = -7
+
+_lib = None
+
+
+class SaasmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"saasm error {code}: {msg}")
+        self.code = code
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("digit_bits", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("items_per_thread", ctypes.c_int32), ("seg_pack", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class Tuning:
+    digit_bits: int = 0
+    block_threads: int = 0
+    items_per_thread: int = 0
+    seg_pack: int = 0
+
+    def c(self):
+        return _Tuning(self.digit_bits, self.block_threads, self.items_per_thread, self.seg_pack)
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def load():
+    """Load libsaasm.so (built in-tree by paper_1404_3456_amd.build); raises when missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise ImportError(f"{_LIB} is missing: build it with `python -m paper_1404_3456_amd.build`")
+    lib = ctypes.CDLL(_LIB)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    TP = ctypes.POINTER(_Tuning)
+    sig = {
+        "sa_version": ([], ctypes.c_char_p),
+        "sa_last_error": ([], ctypes.c_char_p),
+        "sa_packed_words": ([I64], I64),
+        "sa_sepmask_words": ([I64], I64),
+        "sa_pack_ws_bytes": ([I64], I64),
+        "sa_pack": ([P, I64, P, P, P, I64, P, P, I64, P], ctypes.c_int),
+        "sa_sort_ws_bytes": ([I64, TP], I64),
+        "sa_sort_pairs": ([P, P, I64, I32, I32, P, I64, TP, P], ctypes.c_int),
+        "sa_build_ws_bytes": ([I64, TP], I64),
+        "sa_build": ([P, I64, P, P, P, I64, TP, P, P], ctypes.c_int),
+        "sa_lcp_ws_bytes": ([I64], I64),
+        "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
+        "sa_lcp_set_chunk": ([I32], ctypes.c_int),
+        "sa_overlaps_ws_bytes": ([I64, I64], I64),
+        "sa_overlaps": ([P, I64, P, P, P, I32, P, I64, P, P, I64, P, P], ctypes.c_int),
+        "sa_timing_enable": ([I32], ctypes.c_int),
+        "sa_timing_reset": ([], ctypes.c_int),
+        "sa_timing_get": ([ctypes.c_char_p, P, P, P], ctypes.c_int),
+        "sa_copy_u32": ([P, P, I64, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def sa_version() -> str:
+    return load().sa_version().decode()
+
+
+def sa_last_error() -> str:
+    return load().sa_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != SA_OK:
+        raise SaasmError(rc, sa_last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _tune(tuning):
+    if tuning is None:
+        return None
+    if isinstance(tuning, dict):
+        tuning = Tuning(**tuning)
+    return ctypes.byref(tuning.c())
+
+
+def _dev_text(text):
+    torch = _torch()
+    if not isinstance(text, torch.Tensor):
+        import numpy as np
+        text = torch.from_numpy(np.ascontiguousarray(text, dtype=np.uint8))
+    if text.dtype != torch.uint8:
+        raise TypeError("text must be uint8")
+    if not text.is_cuda:
+        text = text.cuda()
+    return text.contiguous()
+
+
+def _ws(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---- entry points --------------------------------------------------------------------------
+
+def sa_build_ws_bytes(n: int, tuning=None) -> int:
+    return int(load().sa_build_ws_bytes(n, _tune(tuning)))
+
+
+def sa_lcp_ws_bytes(n: int) -> int:
+    return int(load().sa_lcp_ws_bytes(n))
+
+
+def sa_overlaps_ws_bytes(n: int, candidates: int = 0) -> int:
+    return int(load().sa_overlaps_ws_bytes(n, candidates))
+
+
+def sa_sort_ws_bytes(n: int, tuning=None) -> int:
+    return int(load().sa_sort_ws_bytes(n, _tune(tuning)))
+
+
+def sa_pack(text, with_read_ends: bool = True, stream=None):
+    """Returns (packed uint32, sepmask uint32, read_end int32 or None)."""
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    packed = torch.empty(int(lib.sa_packed_words(n)), dtype=torch.int32, device=t.device)
+    sepmask = torch.empty(int(lib.sa_sepmask_words(n)), dtype=torch.int32, device=t.device)
+    m = ctypes.c_int64(0)
+    read_end = torch.empty(max(n, 1), dtype=torch.int32, device=t.device) if with_read_ends else None
+    cap = n if with_read_ends else 0
+    ws = _ws(int(lib.sa_pack_ws_bytes(n)), t.device)
+    _check(lib.sa_pack(_ptr(t), n, _ptr(packed), _ptr(sepmask), _ptr(read_end), cap,
+                       ctypes.byref(m), _ptr(ws), ws.numel(), _stream(stream)))
+    if read_end is not None:
+        read_end = read_end[: m.value]
+    return packed, sepmask, read_end
+
+
+def sa_sort_pairs(keys, vals, bit_lo: int = 0, bit_hi: int = 64, tuning=None, stream=None):
+    """Stable in-place sort of (keys int64/uint64, vals int32/uint32) by key bits [lo, hi)."""
+    lib = load()
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and vals differ in length")
+    if not (keys.is_contiguous() and vals.is_contiguous()):
+        raise ValueError("keys and vals must be contiguous")
+    if keys.element_size() != 8 or vals.element_size() != 4:
+        raise TypeError("keys must be 64-bit and vals 32-bit")
+    wsb = sa_sort_ws_bytes(n, tuning)
+    ws = _ws(wsb, keys.device)
+    _check(lib.sa_sort_pairs(_ptr(keys), _ptr(vals), n, bit_lo, bit_hi, _ptr(ws), ws.numel(),
+                             _tune(tuning), _stream(stream)))
+    return keys, vals
+
+
+def sa_build(text, isa: bool = True, tuning=None, stream=None, return_rounds: bool = False):
+    """Suffix array (and inverse) of a '$'-separated text on the GPU."""
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    sa = torch.empty(n, dtype=torch.int32, device=t.device)
+    isa_t = torch.empty(n, dtype=torch.int32, device=t.device) if isa else None
+    wsb = sa_build_ws_bytes(n, tuning)
+    if wsb < 0:
+        raise SaasmError(SA_ERR_INVALID, "bad size or tuning")
+    ws = _ws(wsb, t.device)
+    rounds = ctypes.c_int32(0)
+    _check(lib.sa_build(_ptr(t), n, _ptr(sa), _ptr(isa_t), _ptr(ws), ws.numel(), _tune(tuning),
+                        ctypes.byref(rounds), _stream(stream)))
+    if return_rounds:
+        return sa, isa_t, int(rounds.value)
+    return sa, isa_t
+
+
+def sa_lcp(text, sa, isa, stream=None):
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    lcp = torch.empty(n, dtype=torch.int32, device=t.device)
+    ws = _ws(sa_lcp_ws_bytes(n), t.device)
+    _check(lib.sa_lcp(_ptr(t), n, _ptr(sa), _ptr(isa), _ptr(lcp), _ptr(ws), ws.numel(),
+                      _stream(stream)))
+    return lcp
+
+
+def sa_lcp_set_chunk(chunk: int):
+    _check(load().sa_lcp_set_chunk(int(chunk)))
+
+
+_ovl_ws_hint = {}
+
+
+def sa_overlaps(text, sa, isa, lcp, min_len: int, stream=None):
+    """(k, 3) int32 device tensor of rows (a, b, l), sorted by (a, b)."""
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    need = max(_ovl_ws_hint.get(n, 0), sa_overlaps_ws_bytes(n, 0))
+    cap = max(n // 4, 1024)
+    for _ in range(4):
+        ws = _ws(need, t.device)
+        out = torch.empty((cap, 3), dtype=torch.int32, device=t.device)
+        n_out = ctypes.c_int64(0)
+        needed = ctypes.c_int64(0)
+        rc = lib.sa_overlaps(_ptr(t), n, _ptr(sa), _ptr(isa), _ptr(lcp), int(min_len), _ptr(out),
+                             cap, ctypes.byref(n_out), _ptr(ws), ws.numel(), ctypes.byref(needed),
+                             _stream(stream))
+        if rc == SA_ERR_NOMEM and needed.value > need:
+            need = int(needed.value)
+            _ovl_ws_hint[n] = need
+            continue
+        if rc == SA_ERR_CAPACITY and n_out.value > cap:
+            cap = int(n_out.value)
+            continue
+        _check(rc)
+        return out[: n_out.value]
+    raise SaasmError(SA_ERR_HIP, "sa_overlaps: sizes did not settle")
+
+
+def sa_timing_enable(on: bool = True):
+    _check(load().sa_timing_enable(1 if on else 0))
+
+
+def sa_timing_reset():
+    _check(load().sa_timing_reset())
+
+
+def sa_timing_get(key: str):
+    """(launches, total_ms, total_algorithmic_bytes) for an instrumented kernel key."""
+    lib = load()
+    L = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
+    rc = lib.sa_timing_get(key.encode(), ctypes.byref(L), ctypes.byref(ms), ctypes.byref(by))
+    if rc not in (SA_OK, SA_ERR_NOTFOUND):
+        _check(rc)
+    return int(L.value), float(ms.value), float(by.value)
+
+
+def sa_copy_u32(dst, src, stream=None):
+    n = src.numel()
+    _check(load().sa_copy_u32(_ptr(dst), _ptr(src), n, _stream(stream)))

@@ -1,0 +1,146 @@
+// api.hip -- error reporting, version, tuning resolution and per-kernel event timing.
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace saasm {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string &msg) { t_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+int resolve_tuning(const sa_tuning *tu, Tune *out) {
+    Tune t;
+    if (tu) {
+        if (tu->digit_bits) t.dbits = tu->digit_bits;
+        if (tu->block_threads) t.block = tu->block_threads;
+        if (tu->items_per_thread) t.items = tu->items_per_thread;
+        if (tu->seg_pack != 0) return fail(SA_ERR_INVALID, "seg_pack must be 0 for this call");
+    }
+    if (t.dbits != 4 && t.dbits != 8 && t.dbits != 11)
+        return fail(SA_ERR_INVALID, "digit_bits must be 4, 8 or 11");
+    if (t.block != 256 && t.block != 512) return fail(SA_ERR_INVALID, "block_threads must be 256 or 512");
+    if (t.items != 8 && t.items != 16) return fail(SA_ERR_INVALID, "items_per_thread must be 8 or 16");
+    *out = t;
+    return SA_OK;
+}
+
+// ---- timing ---------------------------------------------------------------------------------
+namespace {
+struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+struct Pending {
+    hipEvent_t a, b;
+    std::string key;
+    double bytes;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, Acc> g_acc;
+
+hipEvent_t get_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool timing_on() { return g_on; }
+
+TimedScope::TimedScope(const char *k, double b, hipStream_t s) : key(k), bytes(b), stream(s) {
+    if (!g_on) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    start = get_event();
+    if (start && hipEventRecord(start, stream) != hipSuccess) {
+        g_pool.push_back(start);
+        start = nullptr;
+    }
+}
+
+void TimedScope::finish() {
+    if (!start) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t end = get_event();
+    if (!end || hipEventRecord(end, stream) != hipSuccess) {
+        g_pool.push_back(start);
+        if (end) g_pool.push_back(end);
+        start = nullptr;
+        return;
+    }
+    g_pending.push_back(Pending{start, end, key, bytes});
+    start = nullptr;
+}
+
+void timing_flush() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &p : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            Acc &a = g_acc[p.key];
+            a.launches += 1;
+            a.ms += ms;
+            a.bytes += p.bytes;
+        }
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+}  // namespace saasm
+
+using namespace saasm;
+
+extern "C" const char *sa_version(void) { return "saasm 0.1 (gfx950)"; }
+
+extern "C" const char *sa_last_error(void) { return t_last_error.c_str(); }
+
+extern "C" int sa_timing_enable(int32_t on) {
+    if (!on) timing_flush();
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_on = on != 0;
+    return SA_OK;
+}
+
+extern "C" int sa_timing_reset(void) {
+    timing_flush();
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_acc.clear();
+    return SA_OK;
+}
+
+extern "C" int sa_timing_get(const char *key, int64_t *launches_h, double *total_ms_h,
+                             double *bytes_h) {
+    if (!key) return fail(SA_ERR_INVALID, "sa_timing_get: NULL key");
+    timing_flush();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_acc.find(key);
+    if (it == g_acc.end()) {
+        if (launches_h) *launches_h = 0;
+        if (total_ms_h) *total_ms_h = 0;
+        if (bytes_h) *bytes_h = 0;
+        return SA_ERR_NOTFOUND;
+    }
+    if (launches_h) *launches_h = it->second.launches;
+    if (total_ms_h) *total_ms_h = it->second.ms;
+    if (bytes_h) *bytes_h = it->second.bytes;
+    return SA_OK;
+}

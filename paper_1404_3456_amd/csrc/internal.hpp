@@ -1,0 +1,121 @@
+// internal.hpp -- host-side plumbing shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/saasm.h"
+
+namespace saasm {
+
+// ---- errors --------------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define SA_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::saasm::fail(SA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define SA_TRY(expr)                 \
+    do {                             \
+        int r_ = (expr);             \
+        if (r_ != SA_OK) return r_;  \
+    } while (0)
+
+constexpr int64_t kMaxN = int64_t(1) << 30;
+constexpr uint32_t kDone = 1u << 31;      // rank word flag: suffix's group is a singleton
+constexpr uint32_t kRankMask = kDone - 1;
+constexpr int kH0 = 29;                   // bases in the first-round key (58 code bits + 5)
+
+// ---- workspace carving -----------------------------------------------------------------------
+struct Carver {
+    char *base;
+    int64_t off = 0;
+    int64_t cap;
+    Carver(void *p, int64_t c) : base(static_cast<char *>(p)), cap(c) {}
+    template <class T>
+    T *take(int64_t count) {
+        off = (off + 255) & ~int64_t(255);
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += count * int64_t(sizeof(T));
+        return p;
+    }
+    bool ok() const { return off <= cap; }
+};
+
+// ---- tuning --------------------------------------------------------------------------------
+struct Tune {
+    int dbits = 8;
+    int block = 256;
+    int items = 16;
+    int tile() const { return block * items; }
+    int radix() const { return 1 << dbits; }
+};
+int resolve_tuning(const sa_tuning *t, Tune *out);
+
+// ---- timing --------------------------------------------------------------------------------
+bool timing_on();
+struct TimedScope {
+    // Records a start event on `stream` when timing is on; finish() records the end event and
+    // files the launch under `key` with `bytes` algorithmic bytes.
+    const char *key;
+    double bytes;
+    hipStream_t stream;
+    hipEvent_t start = nullptr;
+    TimedScope(const char *k, double b, hipStream_t s);
+    void finish();
+};
+void timing_flush();  // resolve pending events (call after a stream synchronisation)
+
+// ---- kernels exposed across translation units ----------------------------------------------
+int64_t packed_words(int64_t n);
+int64_t sepmask_words(int64_t n);
+
+// pack: packed/sepmask/per-word separator counts; err bits OR-ed into *err.
+int launch_pack(const uint8_t *text, int64_t n, uint32_t *packed, uint32_t *sepmask,
+                uint32_t *wordcnt, uint32_t *err, hipStream_t s);
+// exclusive scan of uint32 values into int32 (out[i] = sum of in[0..i)); total -> *total_out
+int64_t scan_flags_words(int64_t n);
+int launch_scan_u32_i32(const uint32_t *in, int32_t *out, int64_t n, int32_t *total_out,
+                        uint64_t *lbflags, uint32_t *ticket, uint32_t *err, hipStream_t s);
+int launch_scan_u32_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total_out,
+                        uint64_t *lbflags, uint32_t *ticket, uint32_t *err, hipStream_t s);
+int launch_read_ends(const uint32_t *sepmask, const int32_t *sepcnt, int64_t n, int32_t *read_end,
+                     hipStream_t s);
+int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+int launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+
+// radix sort plumbing
+struct SortBufs {
+    uint64_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;     // [passes][radix] counts
+    uint32_t *gbase;    // [passes][radix] exclusive bases
+    uint32_t *flags;    // [passes][tiles][radix] look-back words
+    uint32_t *tickets;  // [passes]
+    uint32_t *err;
+};
+int sort_passes(int bits, const Tune &t);
+int64_t sort_flag_words(int64_t n, int bits, const Tune &t);
+void carve_sort(Carver &c, int64_t n, int bits, const Tune &t, SortBufs *b, bool with_items);
+// Clears histogram, flags and tickets for a sort of n items over `bits` bits.
+int sort_prepare(const SortBufs &b, int64_t n, int bits, const Tune &t, hipStream_t s);
+// Histogram of keys[cur] for all passes (when the producer did not build it).
+int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
+                hipStream_t s);
+// Runs the passes; returns the buffer index holding the sorted data in *cur_out.
+int sort_run(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
+             hipStream_t s, int *cur_out);
+
+// key builders (fused with the histogram of the sort that follows)
+int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, const SortBufs &b,
+                int cur, const Tune &t, hipStream_t s);
+int launch_keys_doubling(const uint32_t *rank, int64_t n, int64_t h, int rbits,
+                         const SortBufs &b, int cur, uint64_t *lbflags, uint32_t *ticket,
+                         uint32_t *count_out, const Tune &t, hipStream_t s);
+
+}  // namespace saasm

@@ -1,0 +1,120 @@
+// lcp.hip -- LCP array by Kasai's scan over text positions.
+//
+// The paper builds the suffix array to answer prefix tests between fragments by searching it
+// (Sec. IV); the LCP array beside it turns those tests into interval walks.  For positions p in
+// text order, the common prefix of suffix p with its predecessor in the suffix array is at
+// least the previous one minus one (Kasai et al.), so a scan that carries that bound compares
+// each position only past the carried length.  Here each thread scans one chunk of `chunk`
+// consecutive positions and starts its carry at 0, which keeps the result exact while letting
+// all chunks run in parallel.  Symbols are compared 32 at a time from the 2-bit packed text;
+// a separator in either suffix ends the match (two separators are different symbols).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace saasm {
+
+// 32 bases starting at position a, base 0 in bits 63..62.
+__device__ __forceinline__ uint64_t window64(const uint32_t *__restrict__ packed, uint32_t a) {
+    const uint32_t w = a >> 4, o = a & 15;
+    uint64_t x = (uint64_t(packed[w]) << 32) | packed[w + 1];
+    x <<= 2 * o;
+    if (o) x |= uint64_t(packed[w + 2]) >> (32 - 2 * o);
+    return x;
+}
+
+// Separator bits of positions a .. a+31, position a in bit 31.
+__device__ __forceinline__ uint32_t sepwin32(const uint32_t *__restrict__ sepmask, uint32_t a) {
+    const uint32_t w = a >> 5, o = a & 31;
+    const uint64_t x = (uint64_t(sepmask[w]) << 32) | sepmask[w + 1];
+    return uint32_t((x << o) >> 32);
+}
+
+__global__ __launch_bounds__(256) void k_kasai(const uint32_t *__restrict__ packed,
+                                               const uint32_t *__restrict__ sepmask,
+                                               const int32_t *__restrict__ sa,
+                                               const int32_t *__restrict__ isa,
+                                               int32_t *__restrict__ lcp, uint32_t n,
+                                               uint32_t chunk, uint32_t *err) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t p0 = uint64_t(c) * chunk;
+    if (p0 >= n) return;
+    const uint32_t p1 = uint32_t((p0 + chunk < n) ? p0 + chunk : n);
+    uint32_t h = 0;
+    for (uint32_t p = uint32_t(p0); p < p1; ++p) {
+        const int32_t i = isa[p];
+        if (i <= 0 || uint32_t(i) >= n) {
+            if (i == 0) lcp[0] = 0;
+            else raise_err(err, kErrRange);
+            h = 0;
+            continue;
+        }
+        const uint32_t q = uint32_t(sa[i - 1]);
+        if (q >= n) {
+            raise_err(err, kErrRange);
+            h = 0;
+            continue;
+        }
+        while (true) {
+            if (p + h >= n || q + h >= n) {  // only reachable for a text without final '$'
+                raise_err(err, kErrRange);
+                break;
+            }
+            const uint64_t d = window64(packed, p + h) ^ window64(packed, q + h);
+            const uint32_t sp = sepwin32(sepmask, p + h) | sepwin32(sepmask, q + h);
+            const uint32_t md = d ? uint32_t(__clzll((long long)d)) >> 1 : 32u;
+            const uint32_t ms = sp ? uint32_t(__clz(sp)) : 32u;
+            const uint32_t k = md < ms ? md : ms;
+            h += k;
+            if (k < 32) break;
+        }
+        lcp[i] = int32_t(h);
+        if (h > 0) --h;
+    }
+}
+
+static uint32_t g_lcp_chunk = 16;
+
+}  // namespace saasm
+
+using namespace saasm;
+
+extern "C" int64_t sa_lcp_ws_bytes(int64_t n) {
+    if (n < 1) return -1;
+    Carver c(nullptr, INT64_MAX);
+    c.take<uint32_t>(packed_words(n));
+    c.take<uint32_t>(sepmask_words(n));
+    c.take<uint32_t>(sepmask_words(n));
+    c.take<uint32_t>(64);
+    return c.off + 256;
+}
+
+extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
+                      int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream) {
+    if (!text || !sa || !isa || !lcp || !ws) return fail(SA_ERR_INVALID, "sa_lcp: NULL pointer");
+    if (n < 1) return fail(SA_ERR_INVALID, "sa_lcp: n must be >= 1");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_lcp: n >= 2^30");
+    if (ws_bytes < sa_lcp_ws_bytes(n)) return fail(SA_ERR_NOMEM, "sa_lcp: workspace too small");
+    Carver c(ws, ws_bytes);
+    uint32_t *packed = c.take<uint32_t>(packed_words(n));
+    uint32_t *sepmask = c.take<uint32_t>(sepmask_words(n));
+    uint32_t *wordcnt = c.take<uint32_t>(sepmask_words(n));
+    uint32_t *err = c.take<uint32_t>(64);
+    SA_TRY(launch_fill_u32(err, 1, 0, stream));
+    SA_TRY(launch_pack(text, n, packed, sepmask, wordcnt, err, stream));
+    const uint32_t chunk = g_lcp_chunk;
+    const int64_t threads = (n + chunk - 1) / chunk;
+    // algorithmic bytes: isa[p] (4) + sa[isa[p]-1] (4) + lcp write (4) per position
+    TimedScope ts("kasai", double(n) * 12.0, stream);
+    hipLaunchKernelGGL(k_kasai, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, stream,
+                       packed, sepmask, sa, isa, lcp, uint32_t(n), chunk, err);
+    ts.finish();
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+// Chunk length of the Kasai scan (positions per thread); exposed for tuning sweeps.
+extern "C" int sa_lcp_set_chunk(int32_t chunk) {
+    if (chunk < 1 || chunk > 4096) return fail(SA_ERR_INVALID, "sa_lcp_set_chunk: 1..4096");
+    g_lcp_chunk = uint32_t(chunk);
+    return SA_OK;
+}

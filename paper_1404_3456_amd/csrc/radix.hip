@@ -1,0 +1,576 @@
+// radix.hip -- LSD radix sort of (uint64 key, uint32 value) pairs for gfx950, plus the two key
+// builders of the suffix-array rounds (fused with the sort's digit histograms).
+//
+// Sec. IV describes the radix sort the paper builds the suffix array with: each pass is a
+// counting sort in which an element's output index is the number of elements in lower
+// buckets plus the number already placed in its own bucket, and a pass is (1) a split of each
+// on-chip chunk by the current digit, (2) per-chunk bucket counts stored digit-major, (3) a
+// prefix sum over that table and (4) a scatter.  Alg. 1 is one such split for one bit.
+//
+// Here one pass is one kernel per tile of keys ("onesweep"):
+//   * the digit counts of every pass are taken once, up front (k_hist or the key builders),
+//     and scanned per pass into global digit bases (k_hist_scan);
+//   * each workgroup ranks its tile by digit with wave64 ballots (a d-bit multisplit instead
+//     of d one-bit splits), publishes its per-digit counts in a (tile x digit) table and
+//     reads the prefix of earlier tiles from that table by decoupled look-back -- the prefix
+//     sum of the paper's step (3) done in the same launch;
+//   * it then stages the tile in LDS in digit order and writes each digit's run contiguously,
+//     so the scatter of step (4) is coalesced.
+// Tiles take their index from an atomic ticket, so every tile a look-back waits on is already
+// resident; every wait is bounded (kSpinLimit) so that all waves exit even on a fault.
+#include <type_traits>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace saasm {
+
+int sort_passes(int bits, const Tune &t) { return bits <= 0 ? 0 : (bits + t.dbits - 1) / t.dbits; }
+
+static int64_t sort_tiles(int64_t n, const Tune &t) {
+    int64_t tl = (n + t.tile() - 1) / t.tile();
+    return tl < 1 ? 1 : tl;
+}
+
+int64_t sort_flag_words(int64_t n, int bits, const Tune &t) {
+    return int64_t(sort_passes(bits, t)) * sort_tiles(n, t) * t.radix();
+}
+
+void carve_sort(Carver &c, int64_t n, int bits, const Tune &t, SortBufs *b, bool with_items) {
+    const int P = sort_passes(bits, t) > 0 ? sort_passes(bits, t) : 1;
+    if (with_items) {
+        b->keys[0] = c.take<uint64_t>(n);
+        b->keys[1] = c.take<uint64_t>(n);
+        b->vals[0] = c.take<uint32_t>(n);
+        b->vals[1] = c.take<uint32_t>(n);
+    }
+    b->hist = c.take<uint32_t>(int64_t(P) * t.radix());
+    b->gbase = c.take<uint32_t>(int64_t(P) * t.radix());
+    b->flags = c.take<uint32_t>(sort_flag_words(n, bits, t) > 0 ? sort_flag_words(n, bits, t) : 1);
+    b->tickets = c.take<uint32_t>(64);
+}
+
+int sort_prepare(const SortBufs &b, int64_t n, int bits, const Tune &t, hipStream_t s) {
+    const int P = sort_passes(bits, t);
+    if (P == 0) return SA_OK;
+    SA_TRY(launch_fill_u32(b.hist, int64_t(P) * t.radix(), 0, s));
+    SA_TRY(launch_fill_u32(b.flags, sort_flag_words(n, bits, t), 0, s));
+    SA_TRY(launch_fill_u32(b.tickets, 64, 0, s));
+    return SA_OK;
+}
+
+// ---- digit histograms ---------------------------------------------------------------------
+__device__ __forceinline__ uint64_t field(uint64_t k, int bit_lo, int bits) {
+    k >>= bit_lo;
+    return bits >= 64 ? k : (k & ((uint64_t(1) << bits) - 1));
+}
+
+template <int D>
+__device__ __forceinline__ void hist_add(uint32_t *s_h, uint64_t f, int passes) {
+    constexpr int R = 1 << D;
+    for (int p = 0; p < passes; ++p)
+        atomicAdd(&s_h[p * R + uint32_t((f >> (p * D)) & (R - 1))], 1u);
+}
+
+template <int D>
+__device__ __forceinline__ void hist_flush(const uint32_t *s_h, uint32_t *hist, int passes) {
+    constexpr int R = 1 << D;
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) {
+        uint32_t v = s_h[i];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_hist(const uint64_t *__restrict__ keys, uint32_t n,
+                                              int bit_lo, int bits, int passes,
+                                              uint32_t *__restrict__ hist) {
+    constexpr int R = 1 << D;
+    extern __shared__ uint32_t s_h[];
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        hist_add<D>(s_h, field(keys[i], bit_lo, bits), passes);
+    __syncthreads();
+    hist_flush<D>(s_h, hist, passes);
+}
+
+// Exclusive scan of each pass's R digit counts (one workgroup per pass).
+template <int D>
+__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ hist,
+                                                   uint32_t *__restrict__ gbase) {
+    constexpr int R = 1 << D;
+    constexpr int PER = (R + 255) / 256;
+    __shared__ uint32_t s_w[4];
+    const uint32_t *h = hist + blockIdx.x * R;
+    uint32_t *g = gbase + blockIdx.x * R;
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int d = threadIdx.x * PER + j;
+        v[j] = d < R ? h[d] : 0;
+        sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_sum<256>(sum, s_w, &total);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int d = threadIdx.x * PER + j;
+        if (d < R) g[d] = run;
+        run += v[j];
+    }
+}
+
+static unsigned hist_grid(int64_t n) {
+    int64_t b = (n + 2047) / 2048;
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return unsigned(b);
+}
+
+int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
+                hipStream_t s) {
+    const int P = sort_passes(bits, t);
+    if (P == 0 || n == 0) return SA_OK;
+    size_t lds = size_t(P) * t.radix() * 4;
+    switch (t.dbits) {
+        case 4: hipLaunchKernelGGL(k_hist<4>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
+        case 8: hipLaunchKernelGGL(k_hist<8>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
+        case 11: hipLaunchKernelGGL(k_hist<11>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
+        default: return fail(SA_ERR_INVALID, "unsupported digit width");
+    }
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+// ---- one LSD pass ---------------------------------------------------------------------------
+template <int D, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__ kin,
+                                                    const uint32_t *__restrict__ vin,
+                                                    uint64_t *__restrict__ kout,
+                                                    uint32_t *__restrict__ vout, uint32_t n,
+                                                    uint32_t shift, uint32_t dmask,
+                                                    const uint32_t *__restrict__ gbase,
+                                                    uint32_t *flags, uint32_t *tick,
+                                                    uint32_t *err) {
+    constexpr int R = 1 << D;
+    constexpr int W = BLOCK / kWave;
+    constexpr int TILE = BLOCK * ITEMS;
+    constexpr int DPT = (R + BLOCK - 1) / BLOCK;  // digits owned per thread (blocked)
+    using Cnt = typename std::conditional<(R > 256), uint16_t, uint32_t>::type;
+
+    __shared__ uint32_t s_tile;
+    __shared__ Cnt s_wcnt[W * R];      // per-wave running counts, then per-wave prefixes
+    __shared__ uint32_t s_lstart[R];   // first local slot of each digit
+    __shared__ uint32_t s_gofs[R];     // global output index minus local slot, per digit
+    __shared__ uint32_t s_scan[W];
+    __shared__ uint64_t s_stage[TILE]; // tile in digit order (keys, then values)
+
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    if (tid == 0) s_tile = ticket(tick);
+    for (int i = tid; i < W * R; i += BLOCK) s_wcnt[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t tbase = tile * TILE;
+    const uint32_t wbase = tbase + wave * (ITEMS * kWave);
+
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS];
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        uint32_t idx = wbase + k * kWave + lane;
+        if (idx < n) {
+            key[k] = kin[idx];
+            val[k] = vin[idx];
+        } else {
+            key[k] = 0;
+            val[k] = 0;
+        }
+    }
+
+    // Stable rank of every item among the items of its wave with the same digit: items are
+    // taken in index order (k-major, lane-minor), the running count per digit kept in LDS.
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * kWave + lane;
+        const bool valid = idx < n;
+        const uint32_t dg = valid ? (uint32_t(key[k] >> shift) & dmask) : 0u;
+        uint64_t m = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t bb = ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        if (valid) {
+            const uint64_t lt = m & lanemask_lt();
+            const uint32_t c0 = s_wcnt[wave * R + dg];
+            pos[k] = c0 + uint32_t(popc64(lt));
+            if (lt == 0) s_wcnt[wave * R + dg] = Cnt(c0 + uint32_t(popc64(m)));
+        }
+        wave_sync();
+    }
+    __syncthreads();
+
+    // Per digit: exclusive prefix over waves, and the tile total.
+    uint32_t tot[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = tid * DPT + j;
+        uint32_t run = 0;
+        if (d < R) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                uint32_t c = s_wcnt[w * R + d];
+                s_wcnt[w * R + d] = Cnt(run);
+                run += c;
+            }
+        }
+        tot[j] = run;
+    }
+    // Publish this tile's counts before looking back, so later tiles can proceed.
+    uint32_t *myflags = flags + size_t(tile) * R;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = tid * DPT + j;
+        if (d < R) st_agent(myflags + d, (tile == 0 ? kLb32Inc : kLb32Agg) | tot[j]);
+    }
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) tsum += tot[j];
+    uint32_t tile_total;
+    uint32_t run = block_excl_sum<BLOCK>(tsum, s_scan, &tile_total);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = tid * DPT + j;
+        if (d < R) {
+            uint32_t ex = 0;
+            if (tile > 0) {
+                ex = lookback_digit(flags, int(tile), R, d, err);
+                st_agent(myflags + d, kLb32Inc | (ex + tot[j]));
+            }
+            s_lstart[d] = run;
+            s_gofs[d] = gbase[d] + ex - run;
+            run += tot[j];
+        }
+    }
+    __syncthreads();
+
+    // Stage keys in digit order.
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * kWave + lane;
+        if (idx < n) {
+            const uint32_t dg = uint32_t(key[k] >> shift) & dmask;
+            const uint32_t lp = s_lstart[dg] + uint32_t(s_wcnt[wave * R + dg]) + pos[k];
+            s_stage[lp] = key[k];
+            pos[k] = lp;
+        }
+    }
+    __syncthreads();
+    const uint32_t tcount = (n - tbase) < uint32_t(TILE) ? (n - tbase) : uint32_t(TILE);
+    uint32_t opos[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t lp = j * BLOCK + tid;
+        if (lp < tcount) {
+            const uint64_t kk = s_stage[lp];
+            const uint32_t dg = uint32_t(kk >> shift) & dmask;
+            uint32_t o = lp + s_gofs[dg];
+            if (o >= n) {  // only an inconsistent histogram can get here
+                raise_err(err, kErrRange);
+                o = 0xffffffffu;
+            } else {
+                kout[o] = kk;
+            }
+            opos[j] = o;
+        }
+    }
+    __syncthreads();
+    uint32_t *s_stage32 = reinterpret_cast<uint32_t *>(s_stage);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * kWave + lane;
+        if (idx < n) s_stage32[pos[k]] = val[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t lp = j * BLOCK + tid;
+        if (lp < tcount && opos[j] != 0xffffffffu) vout[opos[j]] = s_stage32[lp];
+    }
+}
+
+template <int D, int BLOCK, int ITEMS>
+static void launch_pass_t(dim3 grid, hipStream_t s, const uint64_t *kin, const uint32_t *vin,
+                          uint64_t *kout, uint32_t *vout, uint32_t n, uint32_t shift,
+                          uint32_t dmask, const uint32_t *gbase, uint32_t *flags, uint32_t *tick,
+                          uint32_t *err) {
+    hipLaunchKernelGGL((k_onesweep<D, BLOCK, ITEMS>), grid, dim3(BLOCK), 0, s, kin, vin, kout,
+                       vout, n, shift, dmask, gbase, flags, tick, err);
+}
+
+template <int D>
+static int launch_pass_d(const Tune &t, dim3 grid, hipStream_t s, const uint64_t *kin,
+                         const uint32_t *vin, uint64_t *kout, uint32_t *vout, uint32_t n,
+                         uint32_t shift, uint32_t dmask, const uint32_t *gbase, uint32_t *flags,
+                         uint32_t *tick, uint32_t *err) {
+    if (t.block == 256 && t.items == 8)
+        launch_pass_t<D, 256, 8>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
+    else if (t.block == 256 && t.items == 16)
+        launch_pass_t<D, 256, 16>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
+    else if (t.block == 512 && t.items == 8)
+        launch_pass_t<D, 512, 8>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
+    else if (t.block == 512 && t.items == 16)
+        launch_pass_t<D, 512, 16>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
+    else
+        return fail(SA_ERR_INVALID, "unsupported tile shape");
+    return SA_OK;
+}
+
+int sort_run(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
+             hipStream_t s, int *cur_out) {
+    const int P = sort_passes(bits, t);
+    *cur_out = cur;
+    if (P == 0 || n <= 1) return SA_OK;
+    const int R = t.radix();
+    switch (t.dbits) {
+        case 4: hipLaunchKernelGGL(k_hist_scan<4>, dim3(P), dim3(256), 0, s, b.hist, b.gbase); break;
+        case 8: hipLaunchKernelGGL(k_hist_scan<8>, dim3(P), dim3(256), 0, s, b.hist, b.gbase); break;
+        case 11: hipLaunchKernelGGL(k_hist_scan<11>, dim3(P), dim3(256), 0, s, b.hist, b.gbase); break;
+        default: return fail(SA_ERR_INVALID, "unsupported digit width");
+    }
+    SA_HIP(hipGetLastError());
+    const int64_t tiles = sort_tiles(n, t);
+    for (int p = 0; p < P; ++p) {
+        const int lo = p * t.dbits;
+        const int width = (bits - lo) < t.dbits ? (bits - lo) : t.dbits;
+        const uint32_t shift = uint32_t(bit_lo + lo);
+        const uint32_t dmask = (1u << width) - 1u;
+        TimedScope ts("radix_pass", double(n) * 24.0, s);
+        int rc = SA_OK;
+        const dim3 grid{unsigned(tiles), 1u, 1u};
+        uint32_t *fl = b.flags + size_t(p) * tiles * R;
+        switch (t.dbits) {
+            case 4: rc = launch_pass_d<4>(t, grid, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            case 8: rc = launch_pass_d<8>(t, grid, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            case 11: rc = launch_pass_d<11>(t, grid, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            default: rc = fail(SA_ERR_INVALID, "unsupported digit width");
+        }
+        ts.finish();
+        if (rc != SA_OK) return rc;
+        SA_HIP(hipGetLastError());
+        cur ^= 1;
+    }
+    *cur_out = cur;
+    return SA_OK;
+}
+
+// ---- key builders ---------------------------------------------------------------------------
+// First-round key of suffix p (h0 = kH0 bases): the 2-bit codes of T[p .. p+min(L_p, h0)),
+// zero-padded to h0 bases, followed by min(L_p, h0) in 5 bits, where L_p is the distance from p
+// to the next separator.  Comparing two such keys as integers orders the suffixes by their
+// first h0 symbols with the separator below every base; keys equal with a length below h0
+// belong to suffixes that end at different separators at the same offset, whose order is
+// their position order (kept by the stable sort, since values are positions).
+__device__ __forceinline__ uint64_t key0_of(const uint32_t *__restrict__ packed,
+                                            const uint32_t *__restrict__ sepmask, uint32_t p) {
+    const uint32_t w = p >> 4, o = p & 15;
+    uint64_t x = (uint64_t(packed[w]) << 32) | packed[w + 1];
+    x <<= 2 * o;
+    if (o) x |= uint64_t(packed[w + 2]) >> (32 - 2 * o);
+    const uint32_t sw = p >> 5, so = p & 31;
+    const uint64_t sm = ((uint64_t(sepmask[sw]) << 32) | sepmask[sw + 1]) << so;
+    uint32_t L = sm ? uint32_t(__clzll((long long)sm)) : 64u;
+    if (L > uint32_t(kH0)) L = kH0;
+    uint64_t code = x >> (64 - 2 * kH0);
+    if (L < uint32_t(kH0)) code &= ~((uint64_t(1) << (2 * (kH0 - L))) - 1);
+    return (code << 5) | L;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_key0(const uint32_t *__restrict__ packed,
+                                              const uint32_t *__restrict__ sepmask, uint32_t n,
+                                              uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ vals, int passes,
+                                              uint32_t *__restrict__ hist) {
+    constexpr int R = 1 << D;
+    extern __shared__ uint32_t s_h[];
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint64_t k = key0_of(packed, sepmask, p);
+        keys[p] = k;
+        vals[p] = p;
+        hist_add<D>(s_h, k, passes);
+    }
+    __syncthreads();
+    hist_flush<D>(s_h, hist, passes);
+}
+
+int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, const SortBufs &b,
+                int cur, const Tune &t, hipStream_t s) {
+    const int bits = 2 * kH0 + 5;
+    const int P = sort_passes(bits, t);
+    size_t lds = size_t(P) * t.radix() * 4;
+    TimedScope ts("keybuild", double(n) * (12.0 + 0.375), s);
+    switch (t.dbits) {
+        case 4: hipLaunchKernelGGL(k_key0<4>, dim3(hist_grid(n)), dim3(256), lds, s, packed, sepmask, uint32_t(n), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 8: hipLaunchKernelGGL(k_key0<8>, dim3(hist_grid(n)), dim3(256), lds, s, packed, sepmask, uint32_t(n), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 11: hipLaunchKernelGGL(k_key0<11>, dim3(hist_grid(n)), dim3(256), lds, s, packed, sepmask, uint32_t(n), b.keys[cur], b.vals[cur], P, b.hist); break;
+        default: return fail(SA_ERR_INVALID, "unsupported digit width");
+    }
+    ts.finish();
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+// Doubling-round keys, built in text order: for every position p whose group is not yet a
+// singleton, key = (rank[p] << rbits) | rank[p + h], value p, compacted in position order.
+// rank holds group labels (the suffix-array index of the group's first member) with kDone set
+// on singletons.  A suffix still in a non-singleton group after a round with prefix length h
+// has at least h symbols before its separator, so p + h stays inside the text.
+constexpr int kKbBlock = 256;
+constexpr int kKbItems = 8;
+constexpr int kKbTile = kKbBlock * kKbItems;
+
+template <int D>
+__global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restrict__ rank,
+                                                       uint32_t n, uint32_t h, int rbits,
+                                                       uint64_t *__restrict__ keys,
+                                                       uint32_t *__restrict__ vals, int passes,
+                                                       uint32_t *__restrict__ hist,
+                                                       uint64_t *lbflags, uint32_t *tick,
+                                                       uint32_t *count_out, uint32_t *err) {
+    constexpr int R = 1 << D;
+    constexpr int W = kKbBlock / kWave;
+    extern __shared__ uint32_t s_h[];
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_chunk[kKbItems * W];
+    __shared__ uint64_t s_excl;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    for (int i = tid; i < passes * R; i += kKbBlock) s_h[i] = 0;
+    if (tid == 0) s_tile = ticket(tick);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t tbase = tile * kKbTile;
+    uint32_t r[kKbItems];
+    uint64_t act[kKbItems];
+#pragma unroll
+    for (int j = 0; j < kKbItems; ++j) {
+        const uint32_t p = tbase + j * kKbBlock + tid;  // striped: wave covers 64 consecutive
+        r[j] = p < n ? rank[p] : kDone;
+        act[j] = ballot((r[j] & kDone) == 0);
+        if (lane == 0) s_chunk[j * W + wave] = uint32_t(popc64(act[j]));
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // chunks are ordered (j, wave); <= 32 of them: one lane each
+        uint32_t c = lane < uint32_t(kKbItems * W) ? s_chunk[lane] : 0u;
+        uint32_t inc = wave_incl_scan<Sum32>(c);
+        uint32_t tile_total = __shfl(inc, kKbItems * W - 1);
+        if (lane < uint32_t(kKbItems * W)) s_chunk[lane] = inc - c;
+        uint64_t ex = lookback_tile<SumOp>(lbflags, int(tile), tile_total, err);
+        if (lane == 0) s_excl = ex;
+        if (lane == 0 && tbase + kKbTile >= n) *count_out = uint32_t(ex + tile_total);
+    }
+    __syncthreads();
+    const uint64_t rmask = (uint64_t(1) << rbits) - 1;
+#pragma unroll
+    for (int j = 0; j < kKbItems; ++j) {
+        const uint32_t p = tbase + j * kKbBlock + tid;
+        if ((r[j] & kDone) == 0) {
+            uint32_t r2 = 0;
+            if (p + h < n) r2 = rank[p + h] & kRankMask;
+            else raise_err(err, kErrRange);
+            const uint64_t k = ((uint64_t(r[j]) & rmask) << rbits) | (uint64_t(r2) & rmask);
+            const uint32_t o = uint32_t(s_excl) + s_chunk[j * W + wave] +
+                               uint32_t(popc64(act[j] & lanemask_lt()));
+            keys[o] = k;
+            vals[o] = p;
+            hist_add<D>(s_h, k, passes);
+        }
+    }
+    __syncthreads();
+    hist_flush<D>(s_h, hist, passes);
+}
+
+int launch_keys_doubling(const uint32_t *rank, int64_t n, int64_t h, int rbits,
+                         const SortBufs &b, int cur, uint64_t *lbflags, uint32_t *tick,
+                         uint32_t *count_out, const Tune &t, hipStream_t s) {
+    const int bits = 2 * rbits;
+    const int P = sort_passes(bits, t);
+    const int64_t tiles = (n + kKbTile - 1) / kKbTile;
+    SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
+    SA_TRY(launch_fill_u32(tick, 1, 0, s));
+    size_t lds = size_t(P) * t.radix() * 4;
+    TimedScope ts("keybuild", double(n) * 4.0, s);
+    switch (t.dbits) {
+        case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(tiles)), dim3(kKbBlock), lds, s, rank, uint32_t(n), uint32_t(h), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, count_out, b.err); break;
+        case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(tiles)), dim3(kKbBlock), lds, s, rank, uint32_t(n), uint32_t(h), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, count_out, b.err); break;
+        case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(tiles)), dim3(kKbBlock), lds, s, rank, uint32_t(n), uint32_t(h), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, count_out, b.err); break;
+        default: return fail(SA_ERR_INVALID, "unsupported digit width");
+    }
+    ts.finish();
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+}  // namespace saasm
+
+// ---- public sort entry point ---------------------------------------------------------------
+using namespace saasm;
+
+extern "C" int64_t sa_sort_ws_bytes(int64_t n, const sa_tuning *tune) {
+    Tune t;
+    if (n < 0 || resolve_tuning(tune, &t) != SA_OK) return -1;
+    Carver c(nullptr, INT64_MAX);
+    SortBufs b;
+    carve_sort(c, n, 64, t, &b, false);
+    c.take<uint64_t>(n);  // second key buffer
+    c.take<uint32_t>(n);  // second value buffer
+    c.take<uint32_t>(64); // error word
+    return c.off + 256;
+}
+
+extern "C" int sa_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo,
+                             int32_t bit_hi, void *ws, int64_t ws_bytes, const sa_tuning *tune,
+                             hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!keys || !vals || !ws)))
+        return fail(SA_ERR_INVALID, "sa_sort_pairs: NULL pointer or negative n");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_sort_pairs: n >= 2^30");
+    if (bit_lo < 0 || bit_hi > 64 || bit_lo >= bit_hi)
+        return fail(SA_ERR_INVALID, "sa_sort_pairs: need 0 <= bit_lo < bit_hi <= 64");
+    Tune t;
+    SA_TRY(resolve_tuning(tune, &t));
+    if (ws_bytes < sa_sort_ws_bytes(n, tune)) return fail(SA_ERR_NOMEM, "sa_sort_pairs: workspace too small");
+    if (n <= 1) return SA_OK;
+    const int bits = bit_hi - bit_lo;
+    Carver c(ws, ws_bytes);
+    SortBufs b;
+    carve_sort(c, n, bits, t, &b, false);
+    b.keys[0] = keys;
+    b.vals[0] = vals;
+    b.keys[1] = c.take<uint64_t>(n);
+    b.vals[1] = c.take<uint32_t>(n);
+    b.err = c.take<uint32_t>(64);
+    if (!c.ok()) return fail(SA_ERR_NOMEM, "sa_sort_pairs: workspace too small");
+    SA_TRY(launch_fill_u32(b.err, 1, 0, stream));
+    SA_TRY(sort_prepare(b, n, bits, t, stream));
+    SA_TRY(launch_hist(b, 0, n, bit_lo, bits, t, stream));
+    int cur = 0;
+    SA_TRY(sort_run(b, 0, n, bit_lo, bits, t, stream, &cur));
+    if (cur == 1) {
+        SA_HIP(hipMemcpyAsync(keys, b.keys[1], size_t(n) * 8, hipMemcpyDeviceToDevice, stream));
+        SA_HIP(hipMemcpyAsync(vals, b.vals[1], size_t(n) * 4, hipMemcpyDeviceToDevice, stream));
+    }
+    uint32_t err = 0;
+    SA_HIP(hipMemcpyAsync(&err, b.err, 4, hipMemcpyDeviceToHost, stream));
+    SA_HIP(hipStreamSynchronize(stream));
+    timing_flush();
+    if (err) return fail(SA_ERR_HIP, "sa_sort_pairs: device consistency check failed (code " + std::to_string(err) + ")");
+    return SA_OK;
+}

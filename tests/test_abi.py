@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every symbol include/*.h declares; host-side argument
+checks run without a GPU (no compute call is made here)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_1404_3456_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w\s\*]*?\b((?:sa|asm)_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ["sa_build", "sa_lcp", "sa_overlaps", "sa_pack", "sa_sort_pairs",
+                     "sa_last_error", "sa_version", "sa_build_ws_bytes"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_python_binding_names_match_abi():
+    import paper_1404_3456_amd as pkg
+    for n in ["sa_build", "sa_lcp", "sa_overlaps", "sa_pack", "sa_sort_pairs"]:
+        assert callable(getattr(pkg, n))
+
+
+def test_version_and_workspace_sizes():
+    assert "gfx950" in _abi.sa_version()
+    assert _abi.sa_build_ws_bytes(1) > 0
+    small = _abi.sa_build_ws_bytes(80_400)
+    big = _abi.sa_build_ws_bytes(50_100_000)
+    assert big > small > 0
+    # about 45 bytes per suffix for the default tuning: keys x2, values x2, slots x2, ranks
+    assert 30 * 50_100_000 < big < 60 * 50_100_000
+    assert _abi.sa_build_ws_bytes(0) == -1
+    assert _abi.sa_build_ws_bytes(10, {"digit_bits": 5}) == -1
+    assert _abi.sa_lcp_ws_bytes(100) > 0
+    assert _abi.sa_overlaps_ws_bytes(100, 0) < _abi.sa_overlaps_ws_bytes(100, 1000)
+
+
+def test_host_argument_checks_without_gpu():
+    lib = _abi.load()
+    P = ctypes.c_void_p
+    assert lib.sa_build(None, 10, None, None, None, 0, None, None, None) == _abi.SA_ERR_INVALID
+    assert "NULL" in _abi.sa_last_error()
+    dummy = P(16)
+    assert lib.sa_build(dummy, 0, dummy, None, dummy, 1 << 20, None, None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_build(dummy, 1 << 30, dummy, None, dummy, 1 << 20, None, None, None) == _abi.SA_ERR_TOO_LARGE
+    assert lib.sa_build(dummy, 100, dummy, None, dummy, 16, None, None, None) == _abi.SA_ERR_NOMEM
+    bad = _abi.Tuning(digit_bits=7).c()
+    assert lib.sa_build(dummy, 100, dummy, None, dummy, 1 << 30, ctypes.byref(bad), None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_sort_pairs(dummy, dummy, 10, 5, 5, dummy, 1 << 20, None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_sort_pairs(dummy, dummy, 10, 0, 65, dummy, 1 << 20, None, None) == _abi.SA_ERR_INVALID
+    n_out = ctypes.c_int64(0)
+    assert lib.sa_overlaps(dummy, 100, dummy, dummy, dummy, 0, dummy, 10, ctypes.byref(n_out),
+                           dummy, 1 << 20, None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_lcp(dummy, 100, dummy, None, dummy, dummy, 1 << 20, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_lcp_set_chunk(0) == _abi.SA_ERR_INVALID
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "_LIB", str(tmp_path / "libsaasm.so"))
+    with pytest.raises(ImportError):
+        _abi.load()

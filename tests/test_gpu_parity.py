@@ -1,0 +1,215 @@
+"""GPU parity: every result of the HIP library, called through the C ABI, against the CPU
+oracle on the same seeded inputs.  Integer work throughout, so every comparison is exact."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1404_3456_amd import synth
+from tests import checks
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1404_3456_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_sa(lib, text, tuning=None):
+    sa, isa = lib.sa_build(dev(text), tuning=tuning)
+    torch.cuda.synchronize()
+    return sa.cpu().numpy(), isa.cpu().numpy()
+
+
+def run_all(lib, text, min_len, tuning=None):
+    t = dev(text)
+    sa, isa = lib.sa_build(t, tuning=tuning)
+    lcp = lib.sa_lcp(t, sa, isa)
+    ovl = lib.sa_overlaps(t, sa, isa, lcp, min_len)
+    torch.cuda.synchronize()
+    return sa.cpu().numpy(), isa.cpu().numpy(), lcp.cpu().numpy(), ovl.cpu().numpy()
+
+
+def assert_parity(lib, text, min_len=1, tuning=None, label=""):
+    sa, isa, lcp, ovl = run_all(lib, text, min_len, tuning)
+    want_sa = oracle.suffix_array(text)
+    assert np.array_equal(sa, want_sa), f"SA mismatch {label}"
+    assert np.array_equal(isa[sa], np.arange(text.size)), f"ISA mismatch {label}"
+    want_lcp = oracle.lcp_array(text, want_sa)
+    assert np.array_equal(lcp, want_lcp), f"LCP mismatch {label}"
+    want_ovl = oracle.overlaps(text, min_len)
+    assert np.array_equal(ovl.reshape(-1, 3), want_ovl), f"overlap mismatch {label}"
+
+
+# ---- packing -------------------------------------------------------------------------------
+
+def test_pack_layout(lib):
+    text = synth.random_dna_reads(1, 300, 0, 70, allow_empty=True)
+    packed, sepmask, read_end = lib.sa_pack(dev(text))
+    packed = packed.cpu().numpy().view(np.uint32)
+    sepmask = sepmask.cpu().numpy().view(np.uint32)
+    n = text.size
+    lut = np.zeros(256, dtype=np.uint32)
+    lut[ord("C")], lut[ord("G")], lut[ord("T")] = 1, 2, 3
+    codes = lut[text]
+    pad = np.zeros(packed.size * 16, dtype=np.uint32)
+    pad[:n] = codes
+    want_p = (pad.reshape(-1, 16) << (30 - 2 * np.arange(16, dtype=np.uint32))).sum(1).astype(np.uint32)
+    assert np.array_equal(packed, want_p)
+    sep = np.zeros(sepmask.size * 32, dtype=np.uint64)
+    sep[:n] = text == ord("$")
+    want_s = (sep.reshape(-1, 32) << (31 - np.arange(32, dtype=np.uint64))).sum(1).astype(np.uint32)
+    assert np.array_equal(sepmask, want_s)
+    assert np.array_equal(read_end.cpu().numpy(), np.flatnonzero(text == ord("$")))
+
+
+def test_pack_rejects_bad_text(lib):
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_pack(dev(np.frombuffer(b"ACGN$", dtype=np.uint8).copy()))
+    assert e.value.code == lib.SA_ERR_ALPHABET
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_build(dev(np.frombuffer(b"ACGT$acgt$", dtype=np.uint8).copy()))
+    assert e.value.code == lib.SA_ERR_ALPHABET
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_build(dev(np.frombuffer(b"ACGT$AC", dtype=np.uint8).copy()))
+    assert e.value.code == lib.SA_ERR_INVALID
+
+
+# ---- radix sort: one pass is a stable counting sort; the whole sort is a stable sort ---------
+
+@pytest.mark.parametrize("tuning", [None, {"digit_bits": 4}, {"digit_bits": 11},
+                                    {"block_threads": 512, "items_per_thread": 8},
+                                    {"block_threads": 256, "items_per_thread": 8}])
+@pytest.mark.parametrize("bits", [(0, 64), (0, 8), (3, 14), (32, 49), (60, 64)])
+def test_sort_pairs_stable(lib, tuning, bits):
+    rng = np.random.default_rng(abs(hash((str(tuning), bits))) % (1 << 31))
+    n = 70_001
+    keys = rng.integers(0, 1 << 63, size=n, dtype=np.int64)
+    keys[::7] = keys[3]  # many equal fields
+    vals = np.arange(n, dtype=np.int32)
+    lo, hi = bits
+    field = (keys.view(np.uint64) >> np.uint64(lo))
+    if hi - lo < 64:
+        field &= np.uint64((1 << (hi - lo)) - 1)
+    order = np.argsort(field, kind="stable")
+    k_t, v_t = dev(keys.copy()), dev(vals.copy())
+    lib.sa_sort_pairs(k_t, v_t, lo, hi, tuning=tuning)
+    assert np.array_equal(v_t.cpu().numpy(), vals[order])
+    assert np.array_equal(k_t.cpu().numpy(), keys[order])
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 255, 4096, 4097, 65536 * 3 + 17])
+def test_sort_pairs_sizes(lib, n):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 1 << 40, size=n, dtype=np.int64)
+    vals = rng.integers(0, 1 << 31, size=n, dtype=np.int32)
+    order = np.argsort(keys, kind="stable")
+    if n == 0:
+        return
+    k_t, v_t = dev(keys.copy()), dev(vals.copy())
+    lib.sa_sort_pairs(k_t, v_t, 0, 40)
+    assert np.array_equal(k_t.cpu().numpy(), keys[order])
+    assert np.array_equal(v_t.cpu().numpy(), vals[order])
+
+
+# ---- suffix array / LCP / overlaps ----------------------------------------------------------
+
+def tiny_dna_texts(max_len=6):
+    out = []
+    for L in range(0, max_len):
+        for body in itertools.product("ACGT$", repeat=L):
+            s = "".join(body) + "$"
+            out.append(np.frombuffer(s.encode(), dtype=np.uint8).copy())
+    return out
+
+
+def test_tiny_exhaustive(lib):
+    texts = tiny_dna_texts(5)
+    rng = np.random.default_rng(5)
+    texts += [t for t in tiny_dna_texts(6) if rng.random() < 0.05]
+    for t in texts:
+        sa, isa = run_sa(lib, t)
+        assert np.array_equal(sa, oracle.suffix_array(t)), t.tobytes()
+
+
+EDGE = {
+    "one_sep": b"$",
+    "two_seps": b"$$",
+    "one_base": b"A$",
+    "empty_reads": b"$AC$$GT$$",
+    "homopolymer_10k": b"A" * 10_000 + b"$",
+    "two_identical": b"ACGTTGCAAC$ACGTTGCAAC$",
+    "many_identical": b"GATTACA$" * 300,
+    "period3_5k": b"ACG" * 1700 + b"$",
+    "two_homopolymers": b"A" * 3000 + b"$" + b"A" * 2999 + b"$",
+    "nested": b"ACGTACGTACGT$CGTACG$GTAC$T$",
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_edge_cases(lib, name):
+    t = np.frombuffer(EDGE[name], dtype=np.uint8).copy()
+    assert_parity(lib, t, min_len=1, label=name)
+    assert_parity(lib, t, min_len=3, label=name)
+
+
+@pytest.mark.parametrize("seed,m,lo,hi,alpha", [
+    (11, 200, 0, 50, b"ACGT"),
+    (12, 400, 0, 120, b"AC"),
+    (13, 2000, 1, 30, b"A"),
+    (14, 50, 500, 2000, b"ACGT"),
+    (15, 3000, 0, 40, b"ACG"),
+])
+def test_ragged_random(lib, seed, m, lo, hi, alpha):
+    t = synth.random_dna_reads(seed, m, lo, hi, alphabet=alpha, allow_empty=True)
+    assert_parity(lib, t, min_len=4, label=f"seed{seed}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_overlapping_reads(lib, seed):
+    t = synth.genome_reads(seed, 3000 + 1000 * seed, 300, 80 + 20 * seed, err=0.01 * (seed % 2),
+                           alphabet_size=2 + seed % 3)
+    assert_parity(lib, t, min_len=15, label=f"genome{seed}")
+
+
+def test_small_plain_workload(lib):
+    r = synth.small_plain()
+    assert_parity(lib, r.text, min_len=r.min_len, label=r.name)
+    # and the positional ground truth for error-free equal-length reads
+    t = dev(r.text)
+    sa, isa = lib.sa_build(t)
+    lcp = lib.sa_lcp(t, sa, isa)
+    ovl = lib.sa_overlaps(t, sa, isa, lcp, r.min_len).cpu().numpy()
+    assert np.array_equal(ovl, checks.positional_overlaps(r.starts, 200, r.min_len))
+
+
+TUNINGS = [{"digit_bits": d, "block_threads": b, "items_per_thread": i}
+           for d in (4, 8, 11) for b, i in ((256, 8), (256, 16), (512, 8), (512, 16))]
+
+
+def test_tunings_identical(lib):
+    """Every digit width and tile shape gives byte-identical results (also a race check)."""
+    t = synth.genome_reads(99, 20_000, 600, 150, err=0.005)
+    want = oracle.suffix_array(t)
+    for tu in TUNINGS:
+        sa, _ = run_sa(lib, t, tu)
+        assert np.array_equal(sa, want), tu
+
+
+def test_repeat_runs_identical(lib):
+    t = synth.genome_reads(7, 50_000, 2000, 100, err=0.005)
+    first = run_all(lib, t, 20)
+    for _ in range(3):
+        again = run_all(lib, t, 20)
+        for a, b in zip(first, again):
+            assert np.array_equal(a, b)
