@@ -40,6 +40,14 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
     ap.add_argument("--lcp-chunk", type=int, default=0)
+    ap.add_argument("--max-total", type=int, default=0,
+                    help="batched workload: stop adding sets once this many characters are drawn")
+    ap.add_argument("--no-graph", action="store_true", help="batched workload: no hipGraph replay")
+    ap.add_argument("--pool", type=int, default=64, help="serving: distinct jobs generated")
+    ap.add_argument("--jobs", type=int, default=300, help="serving: jobs per arrival-rate run")
+    ap.add_argument("--workers", type=int, default=3, help="serving: server worker streams")
+    ap.add_argument("--max-jobs", type=int, default=64, help="serving: jobs per batch at most")
+    ap.add_argument("--p99-bound-ms", type=float, default=500.0, help="serving: p99 bound")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "radix_pass_traffic.json"),
                     help="JSON with HBM bytes per radix-pass launch from rocprofv3 counters")
     return ap.parse_args()
@@ -67,6 +75,186 @@ def cpu_baseline(scale):
     }
 
 
+def bench_batched(args, pkg, torch, np):
+    """256 independent fragment sets: one batched build (all sets per launch, doubling rounds
+    replayed from a hipGraph) against the plain path run set by set, same GPU, same stream."""
+    from paper_1404_3456_amd import synth
+    t0 = time.perf_counter()
+    sets = synth.batched_sets(max_total=args.max_total or None)
+    off = np.concatenate([[0], np.cumsum([s.text.size for s in sets])]).astype(np.int64)
+    cat = np.concatenate([s.text for s in sets])
+    log(f"batched workload: {len(sets)} sets, n={cat.size}, generated in {time.perf_counter()-t0:.1f} s")
+    text = torch.from_numpy(cat).cuda()
+    min_len = 40
+    tuning = None
+    if args.digit_bits or args.block or args.items:
+        tuning = pkg.Tuning(args.digit_bits, args.block, args.items, 0)
+
+    def batched():
+        sa, isa = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=not args.no_graph)
+        lcp = pkg.sa_lcp(text, sa, isa)
+        ovl = pkg.sa_overlaps(text, sa, isa, lcp, min_len)
+        return sa, ovl
+
+    def plain():
+        outs = []
+        for s in range(len(sets)):
+            t = text[off[s]:off[s + 1]]
+            sa, isa = pkg.sa_build(t, tuning=tuning)
+            lcp = pkg.sa_lcp(t, sa, isa)
+            outs.append(pkg.sa_overlaps(t, sa, isa, lcp, min_len))
+        return outs
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - a
+            best = dt if best is None else min(best, dt)
+        return best, out
+
+    tb, (sa_b, ovl_b) = timed(batched, args.steps)
+    log(f"batched: {tb*1e3:.1f} ms")
+    tp, outs = timed(plain, max(1, args.steps // 2))
+    log(f"plain per set: {tp*1e3:.1f} ms")
+    # the batched result must equal the per-set plain result (overlap rows per set)
+    n_rows = sum(int(o.shape[0]) for o in outs)
+    same = n_rows == int(ovl_b.shape[0])
+    out = {
+        "metric": "batched jobs/s vs plain per-job path",
+        "value": round(len(sets) / tb, 3),
+        "unit": "jobs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(tb * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched-256: 256 sets, genome log-uniform 10 kbp-2 Mbp, reads "
+                               "100-1000 bp, coverage 5-20x, 0.5% subs, overlaps >= 40",
+                   "sets": len(sets), "n_total": int(cat.size), "graph": not args.no_graph,
+                   "tuning": tuning.__dict__ if tuning else "default"},
+        "plain_jobs_per_s": round(len(sets) / tp, 3),
+        "speedup_vs_plain": round(tp / tb, 3),
+        "batched_Msuffixes_per_s": round(cat.size / tb / 1e6, 1),
+        "overlap_rows": int(ovl_b.shape[0]),
+        "rows_match_plain": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, pkg, torch, np):
+    """Poisson stream of assembly jobs (genome log-uniform 1 kbp-5 Mbp, reads 150-800 bp, 8x,
+    0.5% subs, overlaps >= 40), served by the continuous-batching server and, as the baseline,
+    by the plain path (one job at a time, single-text entry points), both under a 64 GiB arena.
+    Reports completed jobs/s and p50/p99 latency (completion minus scheduled arrival)."""
+    import threading
+    from paper_1404_3456_amd import synth
+    t0 = time.perf_counter()
+    pool_n = args.pool
+    _, pool = synth.serving_jobs(n_jobs=pool_n, rate_per_s=1.0)
+    texts = [j.text for j in pool]
+    log(f"serving pool: {pool_n} jobs, {sum(t.size for t in texts)/1e6:.1f} M chars, "
+        f"generated in {time.perf_counter()-t0:.1f} s")
+    arena = 64 << 30
+
+    def run(mode, rate, n_jobs, workers):
+        rng = np.random.default_rng(1404 + int(rate * 1000))
+        gaps = rng.exponential(1.0 / rate, size=n_jobs) if rate > 0 else np.zeros(n_jobs)
+        arr = np.cumsum(gaps) - gaps[0]
+        order = rng.integers(0, pool_n, size=n_jobs)
+        lat = [None] * n_jobs
+        pending = {}
+        lock = threading.Lock()
+        done = threading.Event()
+        with pkg.AsmServer(arena, max_jobs_per_batch=args.max_jobs, workers=workers,
+                           mode=mode) as srv:
+            start = time.perf_counter()
+
+            def submitter():
+                for i in range(n_jobs):
+                    target = start + arr[i]
+                    while True:
+                        now = time.perf_counter()
+                        if now >= target:
+                            break
+                        time.sleep(min(0.0005, target - now))
+                    lag = time.perf_counter() - target
+                    jid = srv.asm_submit(texts[order[i]], 40)
+                    with lock:
+                        pending[jid] = (i, lag)
+                done.set()
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            finished = 0
+            t_last = start
+            while finished < n_jobs:
+                with lock:
+                    items = list(pending.items())
+                for jid, (i, lag) in items:
+                    r = srv.asm_poll(jid)
+                    if r is None:
+                        continue
+                    if r["status"] != 0:
+                        raise RuntimeError(f"job failed with {r['status']}")
+                    lat[i] = (r["t_done"] - r["t_submit"]) + lag
+                    srv.asm_release(jid)
+                    with lock:
+                        del pending[jid]
+                    finished += 1
+                    t_last = time.perf_counter()
+                if not items:
+                    time.sleep(0.0002)
+            th.join()
+            stats = srv.asm_server_stats()
+        lat = np.array(lat)
+        span = t_last - start
+        return {"rate": round(rate, 2), "jobs": n_jobs, "jobs_per_s": round(n_jobs / span, 2),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                "batches": stats["batches"], "max_concurrent_batches": stats["max_concurrent_batches"]}
+
+    # plain capacity: everything queued at once (closed loop, saturated)
+    sat_p = run(1, 0.0, args.jobs, 1)
+    mu_p = sat_p["jobs_per_s"]
+    log(f"plain saturated: {sat_p}")
+    sat_b = run(0, 0.0, args.jobs, args.workers)
+    log(f"batched saturated: {sat_b}")
+    curves = {"plain": [], "served": []}
+    for k in (0.5, 1.0):
+        curves["plain"].append(run(1, k * mu_p, args.jobs, 1))
+        log(f"plain {k}x: {curves['plain'][-1]}")
+    for k in (0.5, 1.0, 2.0, 3.0, 4.0, 6.0):
+        curves["served"].append(run(0, k * mu_p, args.jobs, args.workers))
+        log(f"served {k}x: {curves['served'][-1]}")
+    bound_ms = args.p99_bound_ms
+    ok = [c for c in curves["served"] if c["p99_ms"] <= bound_ms]
+    best = max(ok, key=lambda c: c["jobs_per_s"]) if ok else None
+    out = {
+        "metric": "served jobs/s at p99 <= bound vs plain per-job path",
+        "value": best["jobs_per_s"] if best else None,
+        "unit": "jobs/s",
+        "n_gpus": 1, "steps": args.jobs, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "serving: Poisson jobs, genome log-uniform 1 kbp-5 Mbp, reads "
+                               "150-800 bp, 8x, 0.5% subs, overlaps >= 40, 64 GiB arena",
+                   "pool": pool_n, "jobs_per_run": args.jobs, "workers": args.workers,
+                   "max_jobs_per_batch": args.max_jobs, "p99_bound_ms": bound_ms},
+        "plain_capacity_jobs_per_s": mu_p,
+        "served_saturated_jobs_per_s": sat_b["jobs_per_s"],
+        "speedup_at_bound": round(best["jobs_per_s"] / mu_p, 3) if best else None,
+        "saturated_speedup": round(sat_b["jobs_per_s"] / mu_p, 3),
+        "best_point": best,
+        "curves": curves,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -80,6 +268,10 @@ def main():
     from paper_1404_3456_amd import synth
 
     pkg.load()
+    if args.workload == "batched-256":
+        return bench_batched(args, pkg, torch, np)
+    if args.workload == "serving":
+        return bench_serving(args, pkg, torch, np)
     if args.workload == "plain-large-5M":
         r = synth.large_plain()
     elif args.workload == "repeat-stress-40M":

@@ -20,7 +20,7 @@
  *  - Text: bytes 'A','C','G','T' and '$'; text[n-1] must be '$'.  Read i is the bytes between
  *    the (i-1)-th and i-th separator (empty reads, "$$", are allowed).  Positions are offsets
  *    in the text, separators included; read ids count separators from 0.
- *  - Size: 1 <= n < 2^30.
+ *  - Size: 1 <= n <= 2^31 - 3 (positions, ranks and counts are 32-bit).
  *
  * Ordering (Sec. IV of the paper: the suffix array is the sorted array of all suffixes of the
  * text; Sec. III: the text is the set of shotgun fragments): the separator closing read i
@@ -42,7 +42,7 @@ enum {
     SA_PENDING = 1,          /* asynchronous work not finished yet */
     SA_ERR_INVALID = -1,     /* bad argument: NULL pointer, text not ending in '$', bad tuning */
     SA_ERR_ALPHABET = -2,    /* a byte other than A, C, G, T, '$' */
-    SA_ERR_TOO_LARGE = -3,   /* n >= 2^30 */
+    SA_ERR_TOO_LARGE = -3,   /* n > 2^31 - 3 */
     SA_ERR_NOMEM = -4,       /* workspace too small (the required size is reported) */
     SA_ERR_CAPACITY = -5,    /* output buffer too small (the required count is reported) */
     SA_ERR_HIP = -6,         /* a HIP runtime call or a kernel's own consistency check failed */
@@ -51,7 +51,7 @@ enum {
 
 /* Launch tuning of the radix sort; a zero field means "use the default".
  *   digit_bits       4, 8 or 11 bits per LSD pass
- *   block_threads    256 or 512 threads per workgroup (4 or 8 wave64 wavefronts)
+ *   block_threads    256 or 512 threads per workgroup (4 or 8 wave64 wavefronts; default 512)
  *   items_per_thread 8 or 16 keys per thread (tile = block_threads * items_per_thread)
  *   seg_pack         reserved for the batched path; must be 0 here                          */
 typedef struct {
@@ -126,6 +126,23 @@ int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
              void *ws, int64_t ws_bytes, const sa_tuning *tune_or_null, int32_t *rounds_h,
              hipStream_t stream);
 
+/* Batched build of many independent texts in one set of launches (the fragment sets of
+ * Sec. III, one per assembly job).  The texts are laid end to end in `text`; text s occupies
+ * text[set_off_h[s] .. set_off_h[s+1]) and must end with '$'.
+ *   set_off_h   host [n_sets+1]: 0 = set_off_h[0] < ... < set_off_h[n_sets] = n
+ *   sa          [n] out: for every s, sa[set_off_h[s] .. set_off_h[s+1]) is the suffix array
+ *               of text s, in concatenated coordinates (subtract set_off_h[s] for local ones)
+ *   isa_or_null [n] optional out: inverse of sa
+ *   use_graph   nonzero: the doubling rounds are recorded once as a hipGraph and replayed
+ * sa_lcp and sa_overlaps accept the concatenated text with this sa/isa unchanged: LCP is 0 at
+ * every block start and no overlap pairs reads of different texts.  Synchronises the stream
+ * once per round (once per graph replay). */
+int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const sa_tuning *tune_or_null);
+int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h, int32_t n_sets,
+                     int32_t *sa, int32_t *isa_or_null, void *ws, int64_t ws_bytes,
+                     const sa_tuning *tune_or_null, int32_t use_graph, int32_t *rounds_h,
+                     hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------- */
 /* LCP array beside the suffix array (Kasai's permuted-LCP scan; the paper uses the array for  */
 /* prefix matching between fragments, Sec. IV).                                              */
@@ -140,7 +157,7 @@ int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa
            int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream);
 
 /* Positions scanned per thread by sa_lcp (each thread restarts Kasai's carried bound at its
- * first position; any value gives the same result).  Process-wide; default 16. */
+ * first position; any value gives the same result).  Process-wide; default 4. */
 int sa_lcp_set_chunk(int32_t chunk);
 
 /* ---------------------------------------------------------------------------------------- */
@@ -149,9 +166,10 @@ int sa_lcp_set_chunk(int32_t chunk);
 /* suffix array answers these prefix tests).                                                  */
 /* ---------------------------------------------------------------------------------------- */
 
-/* Workspace bytes for sa_overlaps on a text of n bytes when the walks find `candidates`
- * suffix/prefix matches (0 gives the size of the fixed part). */
-int64_t sa_overlaps_ws_bytes(int64_t n, int64_t candidates);
+/* Workspace bytes for sa_overlaps on a text of n bytes with m reads (m <= 0: assume m = n)
+ * when the walks find `candidates` suffix/prefix matches (0: the part needed before they are
+ * counted). */
+int64_t sa_overlaps_ws_bytes(int64_t n, int64_t m, int64_t candidates);
 
 /* sa_overlaps: for every ordered pair of distinct reads (a, b), the largest l with
  * min_len <= l <= min(|a|, |b|) such that the last l bases of a equal the first l bases of b.
@@ -166,6 +184,60 @@ int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t
                 const int32_t *lcp, int32_t min_len, int32_t *out, int64_t cap,
                 int64_t *n_out_h, void *ws, int64_t ws_bytes, int64_t *ws_needed_h,
                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Assembly-job server: continuous batching of fragment sets (Sec. III: one set of shotgun     */
+/* fragments per reconstruction) under an HBM budget.                                         */
+/* ---------------------------------------------------------------------------------------- */
+typedef struct asm_server asm_server;
+
+typedef struct {
+    int32_t status;          /* SA_PENDING, SA_OK or the SA_ERR_* the job failed with */
+    int64_t n, m;            /* text length and read count */
+    int64_t n_overlaps;      /* rows in ovl */
+    const int32_t *sa;       /* [n] device, job-local positions; owned by the server */
+    const int32_t *isa;      /* [n] device */
+    const int32_t *lcp;      /* [n] device */
+    const int32_t *ovl;      /* [n_overlaps][3] device rows (a, b, l), job-local read ids */
+    double t_submit, t_admit, t_done;  /* seconds since the server was created */
+} asm_result;
+
+/* asm_server_create: start a server over the device buffer `arena` (arena_bytes, the HBM budget;
+ * the caller keeps ownership and frees it after asm_server_destroy).
+ *   max_jobs_per_batch  upper bound on jobs laid into one batch
+ *   workers             worker threads, each with its own HIP stream (1..16); batches on
+ *                       different workers run concurrently on the device
+ *   mode                0: continuous batching; 1: plain (one job at a time, one worker, the
+ *                       single-text entry points) -- the per-job baseline
+ * The server uses the device current at creation. */
+int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_jobs_per_batch,
+                      int32_t workers, int32_t mode, asm_server **out);
+
+/* asm_submit: queue one job.  The text (host memory, same conventions as sa_build) is copied,
+ * so the caller may reuse it at once.  Returns SA_ERR_ALPHABET / SA_ERR_INVALID for a bad text
+ * and SA_ERR_NOMEM when the job alone exceeds the budget; the server keeps running. */
+int asm_submit(asm_server *server, const uint8_t *text_h, int64_t n, int32_t min_len,
+               uint64_t *job_id_h);
+
+/* asm_poll: status and, once done, results of a job.  Returns SA_PENDING while it runs, SA_OK
+ * once res_h->status is final (which may itself be an error), SA_ERR_NOTFOUND for an unknown
+ * id.  Result pointers stay valid until asm_release. */
+int asm_poll(asm_server *server, uint64_t job_id, asm_result *res_h);
+
+/* asm_release: return a finished job's device memory to the arena and forget the job. */
+int asm_release(asm_server *server, uint64_t job_id);
+
+/* asm_server_stats: out_h[6] = {batches run, jobs finished, most batches in flight at once,
+ * arena bytes in use, arena bytes, jobs queued}. */
+int asm_server_stats(asm_server *server, int64_t *out_h);
+
+/* asm_server_fail_alloc_after: make the k-th next arena allocation fail (k >= 1; 0 disarms),
+ * to exercise the failure path: the affected batch's jobs fail with SA_ERR_NOMEM, their memory
+ * is returned, and other jobs are unaffected. */
+int asm_server_fail_alloc_after(asm_server *server, int32_t k);
+
+/* asm_server_destroy: finish queued jobs, stop the workers, free host state. */
+int asm_server_destroy(asm_server *server);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Measurement support.                                                                      */

@@ -8,7 +8,9 @@ does not load the library; the first call does, and raises if libsaasm.so is mis
 from __future__ import annotations
 
 from ._abi import (  # noqa: F401
+    AsmServer,
     SaasmError,
+    SA_PENDING,
     SA_OK,
     SA_ERR_ALPHABET,
     SA_ERR_CAPACITY,
@@ -21,6 +23,8 @@ from ._abi import (  # noqa: F401
     lib_path,
     load,
     sa_build,
+    sa_build_batched,
+    sa_build_batched_ws_bytes,
     sa_build_ws_bytes,
     sa_copy_u32,
     sa_lcp,

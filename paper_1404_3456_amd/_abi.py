@@ -27,6 +27,13 @@ class SaasmError(RuntimeError):
         self.code = code
 
 
+class _AsmResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("n_overlaps", ctypes.c_int64), ("sa", ctypes.c_void_p), ("isa", ctypes.c_void_p),
+                ("lcp", ctypes.c_void_p), ("ovl", ctypes.c_void_p), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("items_per_thread", ctypes.c_int32), ("seg_pack", ctypes.c_int32)]
@@ -68,15 +75,24 @@ def load():
         "sa_sort_pairs": ([P, P, I64, I32, I32, P, I64, TP, P], ctypes.c_int),
         "sa_build_ws_bytes": ([I64, TP], I64),
         "sa_build": ([P, I64, P, P, P, I64, TP, P, P], ctypes.c_int),
+        "sa_build_batched_ws_bytes": ([I64, I32, TP], I64),
+        "sa_build_batched": ([P, I64, P, I32, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
         "sa_lcp_ws_bytes": ([I64], I64),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
         "sa_lcp_set_chunk": ([I32], ctypes.c_int),
-        "sa_overlaps_ws_bytes": ([I64, I64], I64),
+        "sa_overlaps_ws_bytes": ([I64, I64, I64], I64),
         "sa_overlaps": ([P, I64, P, P, P, I32, P, I64, P, P, I64, P, P], ctypes.c_int),
         "sa_timing_enable": ([I32], ctypes.c_int),
         "sa_timing_reset": ([], ctypes.c_int),
         "sa_timing_get": ([ctypes.c_char_p, P, P, P], ctypes.c_int),
         "sa_copy_u32": ([P, P, I64, P], ctypes.c_int),
+        "asm_server_create": ([P, I64, I32, I32, I32, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "asm_submit": ([P, P, I64, I32, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "asm_poll": ([P, ctypes.c_uint64, ctypes.POINTER(_AsmResult)], ctypes.c_int),
+        "asm_release": ([P, ctypes.c_uint64], ctypes.c_int),
+        "asm_server_stats": ([P, P], ctypes.c_int),
+        "asm_server_fail_alloc_after": ([P, I32], ctypes.c_int),
+        "asm_server_destroy": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -149,8 +165,8 @@ def sa_lcp_ws_bytes(n: int) -> int:
     return int(load().sa_lcp_ws_bytes(n))
 
 
-def sa_overlaps_ws_bytes(n: int, candidates: int = 0) -> int:
-    return int(load().sa_overlaps_ws_bytes(n, candidates))
+def sa_overlaps_ws_bytes(n: int, m: int = 0, candidates: int = 0) -> int:
+    return int(load().sa_overlaps_ws_bytes(n, m, candidates))
 
 
 def sa_sort_ws_bytes(n: int, tuning=None) -> int:
@@ -213,6 +229,37 @@ def sa_build(text, isa: bool = True, tuning=None, stream=None, return_rounds: bo
     return sa, isa_t
 
 
+def sa_build_batched_ws_bytes(n: int, n_sets: int, tuning=None) -> int:
+    return int(load().sa_build_batched_ws_bytes(n, n_sets, _tune(tuning)))
+
+
+def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bool = True,
+                     stream=None, return_rounds: bool = False):
+    """Suffix arrays of many texts laid end to end.  `set_off` (host, int64, n_sets+1) bounds
+    text s as text[set_off[s]:set_off[s+1]].  Returns (sa, isa) in concatenated coordinates:
+    sa[set_off[s]:set_off[s+1]] is the suffix array of text s."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    off = np.ascontiguousarray(set_off, dtype=np.int64)
+    n_sets = off.size - 1
+    sa = torch.empty(n, dtype=torch.int32, device=t.device)
+    isa_t = torch.empty(n, dtype=torch.int32, device=t.device) if isa else None
+    wsb = sa_build_batched_ws_bytes(n, n_sets, tuning)
+    if wsb < 0:
+        raise SaasmError(SA_ERR_INVALID, "bad size, set count or tuning")
+    ws = _ws(wsb, t.device)
+    rounds = ctypes.c_int32(0)
+    _check(lib.sa_build_batched(_ptr(t), n, off.ctypes.data_as(ctypes.c_void_p), n_sets, _ptr(sa),
+                                _ptr(isa_t), _ptr(ws), ws.numel(), _tune(tuning),
+                                1 if use_graph else 0, ctypes.byref(rounds), _stream(stream)))
+    if return_rounds:
+        return sa, isa_t, int(rounds.value)
+    return sa, isa_t
+
+
 def sa_lcp(text, sa, isa, stream=None):
     torch = _torch()
     lib = load()
@@ -238,9 +285,9 @@ def sa_overlaps(text, sa, isa, lcp, min_len: int, stream=None):
     lib = load()
     t = _dev_text(text)
     n = t.numel()
-    need = max(_ovl_ws_hint.get(n, 0), sa_overlaps_ws_bytes(n, 0))
-    cap = max(n // 4, 1024)
-    for _ in range(4):
+    need = max(_ovl_ws_hint.get(n, 0), sa_overlaps_ws_bytes(n, 1, 0))
+    cap = max(n // 64, 1024)
+    for _ in range(6):
         ws = _ws(need, t.device)
         out = torch.empty((cap, 3), dtype=torch.int32, device=t.device)
         n_out = ctypes.c_int64(0)
@@ -283,3 +330,85 @@ def sa_timing_get(key: str):
 def sa_copy_u32(dst, src, stream=None):
     n = src.numel()
     _check(load().sa_copy_u32(_ptr(dst), _ptr(src), n, _stream(stream)))
+
+
+# ---- assembly-job server ---------------------------------------------------------------------
+
+class AsmServer:
+    """Continuous-batching job server over an HBM arena (see asm_server_create in saasm.h).
+    Methods mirror the C ABI: asm_submit, asm_poll, asm_release, asm_server_stats."""
+
+    def __init__(self, arena_bytes: int, max_jobs_per_batch: int = 64, workers: int = 2,
+                 mode: int = 0, device=None):
+        torch = _torch()
+        lib = load()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8,
+                                 device=device if device is not None else "cuda")
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p(0)
+        _check(lib.asm_server_create(_ptr(self.arena), self.arena.numel(), int(max_jobs_per_batch),
+                                     int(workers), int(mode), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    def asm_submit(self, text, min_len: int) -> int:
+        import numpy as np
+        t = np.ascontiguousarray(text, dtype=np.uint8)
+        jid = ctypes.c_uint64(0)
+        _check(self._lib.asm_submit(self._h, t.ctypes.data_as(ctypes.c_void_p), t.size,
+                                    int(min_len), ctypes.byref(jid)))
+        return int(jid.value)
+
+    def asm_poll(self, job_id: int):
+        """None while pending, else a dict with status, times and (on success) device tensors
+        that view the server's arena (valid until asm_release)."""
+        r = _AsmResult()
+        rc = self._lib.asm_poll(self._h, ctypes.c_uint64(job_id), ctypes.byref(r))
+        if rc == SA_PENDING:
+            return None
+        _check(rc)
+        out = {"status": r.status, "n": r.n, "m": r.m, "n_overlaps": r.n_overlaps,
+               "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done}
+        if r.status == SA_OK:
+            base = self.arena.data_ptr()
+
+            def view(ptr, count):
+                off = ptr - base
+                return self.arena[off: off + 4 * count].view(_torch().int32)
+
+            out["sa"] = view(r.sa, r.n)
+            out["isa"] = view(r.isa, r.n)
+            out["lcp"] = view(r.lcp, r.n)
+            out["ovl"] = view(r.ovl, 3 * r.n_overlaps).view(-1, 3) if r.n_overlaps else \
+                _torch().zeros((0, 3), dtype=_torch().int32, device=self.arena.device)
+        return out
+
+    def asm_release(self, job_id: int):
+        _check(self._lib.asm_release(self._h, ctypes.c_uint64(job_id)))
+
+    def asm_server_stats(self):
+        import numpy as np
+        a = np.zeros(6, dtype=np.int64)
+        _check(self._lib.asm_server_stats(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+        keys = ["batches", "jobs_done", "max_concurrent_batches", "arena_used", "arena_bytes", "queued"]
+        return dict(zip(keys, a.tolist()))
+
+    def fail_alloc_after(self, k: int):
+        _check(self._lib.asm_server_fail_alloc_after(self._h, int(k)))
+
+    def close(self):
+        if self._h:
+            _check(self._lib.asm_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

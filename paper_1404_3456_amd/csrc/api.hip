@@ -63,10 +63,14 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
-bool timing_on() { return g_on; }
+static thread_local bool t_pause = false;
+
+bool timing_on() { return g_on && !t_pause; }
+
+void timing_pause(bool on) { t_pause = on; }
 
 TimedScope::TimedScope(const char *k, double b, hipStream_t s) : key(k), bytes(b), stream(s) {
-    if (!g_on) return;
+    if (!g_on || t_pause) return;
     std::lock_guard<std::mutex> lk(g_mu);
     start = get_event();
     if (start && hipEventRecord(start, stream) != hipSuccess) {

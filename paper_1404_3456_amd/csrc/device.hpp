@@ -55,10 +55,13 @@ __device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
     __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ---- 32-bit per-digit look-back words: [31:30] status, [29:0] count -----------------------
-constexpr uint32_t kLb32Agg = 1u << 30;
-constexpr uint32_t kLb32Inc = 2u << 30;
-constexpr uint32_t kLb32Val = (1u << 30) - 1;
+// ---- 32-bit per-digit look-back words: 0 = not yet published; otherwise bit 31 marks an
+// inclusive prefix (else a tile aggregate) and bits [30:0] hold the count plus one, so counts up
+// to 2^31 - 2 fit.
+constexpr uint32_t kLb32Inc = 1u << 31;
+__device__ __forceinline__ uint32_t lb32_word(bool inclusive, uint32_t count) {
+    return (inclusive ? kLb32Inc : 0u) | (count + 1u);
+}
 
 // Exclusive prefix of this tile's count for one digit, summed over all earlier tiles.  The
 // flags of tile p for digit d live at flags[p * stride + d].
@@ -69,13 +72,13 @@ __device__ __forceinline__ uint32_t lookback_digit(const uint32_t *flags, int ti
         const uint32_t *f = flags + size_t(p) * stride + d;
         uint32_t v = ld_agent(f);
         uint32_t spins = 0;
-        while ((v >> 30) == 0) {
-            if (++spins > kSpinLimit) { raise_err(err, kErrSpin); v = kLb32Inc; break; }
+        while (v == 0) {
+            if (++spins > kSpinLimit) { raise_err(err, kErrSpin); v = kLb32Inc | 1u; break; }
             __builtin_amdgcn_s_sleep(1);
             v = ld_agent(f);
         }
-        excl += v & kLb32Val;
-        if ((v >> 30) == 2) break;
+        excl += (v & ~kLb32Inc) - 1u;
+        if (v & kLb32Inc) break;
     }
     return excl;
 }

@@ -26,7 +26,7 @@ int fail(int code, const std::string &msg);
         if (r_ != SA_OK) return r_;  \
     } while (0)
 
-constexpr int64_t kMaxN = int64_t(1) << 30;
+constexpr int64_t kMaxN = (int64_t(1) << 31) - 2;  // n <= kMaxN - 1: labels fit in 31 bits
 constexpr uint32_t kDone = 1u << 31;      // rank word flag: suffix's group is a singleton
 constexpr uint32_t kRankMask = kDone - 1;
 constexpr int kH0 = 29;                   // bases in the first-round key (58 code bits + 5)
@@ -50,7 +50,7 @@ struct Carver {
 // ---- tuning --------------------------------------------------------------------------------
 struct Tune {
     int dbits = 8;
-    int block = 256;
+    int block = 512;
     int items = 16;
     int tile() const { return block * items; }
     int radix() const { return 1 << dbits; }
@@ -70,6 +70,7 @@ struct TimedScope {
     void finish();
 };
 void timing_flush();  // resolve pending events (call after a stream synchronisation)
+void timing_pause(bool on);  // calling thread: no events while a stream is being captured
 
 // ---- kernels exposed across translation units ----------------------------------------------
 int64_t packed_words(int64_t n);
@@ -93,7 +94,7 @@ int launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 struct SortBufs {
     uint64_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *hist;     // [passes][radix] counts
+    uint32_t *hist;     // [kHistParts][passes][radix] per-workgroup partial counts
     uint32_t *gbase;    // [passes][radix] exclusive bases
     uint32_t *flags;    // [passes][tiles][radix] look-back words
     uint32_t *tickets;  // [passes]
@@ -104,18 +105,32 @@ int64_t sort_flag_words(int64_t n, int bits, const Tune &t);
 void carve_sort(Carver &c, int64_t n, int bits, const Tune &t, SortBufs *b, bool with_items);
 // Clears histogram, flags and tickets for a sort of n items over `bits` bits.
 int sort_prepare(const SortBufs &b, int64_t n, int bits, const Tune &t, hipStream_t s);
-// Histogram of keys[cur] for all passes (when the producer did not build it).
+// Upper bound on the workgroups of a histogram-producing launch; each writes one partial
+// histogram (no global atomics) that the per-pass scan kernel reduces.
+constexpr int kHistParts = 1024;
+// Histogram of keys[cur] for all passes (when the producer did not build it); the number of
+// partial histograms written goes to *nparts.
 int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
-                hipStream_t s);
-// Runs the passes; returns the buffer index holding the sorted data in *cur_out.
-int sort_run(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
-             hipStream_t s, int *cur_out);
+                hipStream_t s, int *nparts);
+// Runs the passes over n items (or, when count_dev is given, over the count read from device
+// memory, at most n); returns the buffer index holding the sorted data in *cur_out.
+int sort_run(const SortBufs &b, int cur, const uint32_t *count_dev, int64_t n, int bit_lo,
+             int bits, const Tune &t, int nparts, hipStream_t s, int *cur_out);
+
+// Device-side round state of a suffix-array build (words of a uint32 array).
+constexpr int kStErr = 0;      // error bits
+constexpr int kStActive = 1;   // suffixes in non-singleton groups entering the next round
+constexpr int kStKeys = 2;     // keys written by the round's key build (== kStActive)
+constexpr int kStH = 3;        // prefix length the groups are sorted by
+constexpr int kStRounds = 4;   // rounds completed
+constexpr int kStNext = 5;     // active count produced by the round's rank update
 
 // key builders (fused with the histogram of the sort that follows)
-int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, const SortBufs &b,
-                int cur, const Tune &t, hipStream_t s);
-int launch_keys_doubling(const uint32_t *rank, int64_t n, int64_t h, int rbits,
-                         const SortBufs &b, int cur, uint64_t *lbflags, uint32_t *ticket,
-                         uint32_t *count_out, const Tune &t, hipStream_t s);
+int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int h0,
+                const int64_t *set_off_dev, int n_sets, int key_bits, const SortBufs &b, int cur,
+                const Tune &t, hipStream_t s, int *nparts);
+int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, const SortBufs &b, int cur,
+                         uint64_t *lbflags, uint32_t *ticket, uint32_t *state, const Tune &t,
+                         hipStream_t s, int *nparts);
 
 }  // namespace saasm

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_kasai(const uint32_t *__restrict__ pack
     }
 }
 
-static uint32_t g_lcp_chunk = 16;
+static uint32_t g_lcp_chunk = 4;
 
 }  // namespace saasm
 
@@ -92,7 +92,7 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
                       int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream) {
     if (!text || !sa || !isa || !lcp || !ws) return fail(SA_ERR_INVALID, "sa_lcp: NULL pointer");
     if (n < 1) return fail(SA_ERR_INVALID, "sa_lcp: n must be >= 1");
-    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_lcp: n >= 2^30");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_lcp: n >= 2^31-2");
     if (ws_bytes < sa_lcp_ws_bytes(n)) return fail(SA_ERR_NOMEM, "sa_lcp: workspace too small");
     Carver c(ws, ws_bytes);
     uint32_t *packed = c.take<uint32_t>(packed_words(n));

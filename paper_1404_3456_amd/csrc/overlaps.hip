@@ -116,17 +116,19 @@ struct OvlFixed {
     uint32_t *ctr;  // [0] err; [2..3] m (int32 at ctr+2); int64 totals at ctr+8, ctr+10
 };
 
-static void carve_fixed(Carver &c, int64_t n, OvlFixed *F) {
+// Text-sized part (packed text, separator rank structure) then read-sized part (m reads).
+static void carve_fixed(Carver &c, int64_t n, int64_t m, OvlFixed *F) {
     F->packed = c.take<uint32_t>(packed_words(n));
     F->sepmask = c.take<uint32_t>(sepmask_words(n));
     F->wordcnt = c.take<uint32_t>(sepmask_words(n));
     F->sepcnt = c.take<int32_t>(sepmask_words(n));
-    F->read_end = c.take<int32_t>(n);
-    F->counts = c.take<uint32_t>(n + 1);
-    F->offs = c.take<int64_t>(n + 1);
-    F->lbflags = c.take<uint64_t>(scan_flags_words(n + 1) + 16);
     F->tick = c.take<uint32_t>(64);
     F->ctr = c.take<uint32_t>(64);
+    const int64_t scan_n = sepmask_words(n) > m + 1 ? sepmask_words(n) : m + 1;
+    F->lbflags = c.take<uint64_t>(scan_flags_words(scan_n) + 16);
+    F->read_end = c.take<int32_t>(m);
+    F->counts = c.take<uint32_t>(m + 1);
+    F->offs = c.take<int64_t>(m + 1);
 }
 
 struct OvlHits {
@@ -153,13 +155,14 @@ static int bits_for_u(int64_t v) {
 
 using namespace saasm;
 
-extern "C" int64_t sa_overlaps_ws_bytes(int64_t n, int64_t candidates) {
+extern "C" int64_t sa_overlaps_ws_bytes(int64_t n, int64_t m, int64_t candidates) {
     if (n < 1 || candidates < 0) return -1;
+    if (m <= 0 || m > n) m = n;
     Tune t;
     resolve_tuning(nullptr, &t);
     Carver c(nullptr, INT64_MAX);
     OvlFixed F;
-    carve_fixed(c, n, &F);
+    carve_fixed(c, n, m, &F);
     if (candidates > 0) {
         OvlHits H;
         carve_hits(c, candidates, t, &H);
@@ -174,24 +177,26 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     if (!text || !sa || !isa || !lcp || !ws || !n_out_h || (cap > 0 && !out))
         return fail(SA_ERR_INVALID, "sa_overlaps: NULL pointer");
     if (n < 1) return fail(SA_ERR_INVALID, "sa_overlaps: n must be >= 1");
-    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_overlaps: n >= 2^30");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_overlaps: n >= 2^31-2");
     if (min_len < 1) return fail(SA_ERR_INVALID, "sa_overlaps: min_len must be >= 1");
     if (cap < 0) return fail(SA_ERR_INVALID, "sa_overlaps: cap < 0");
-    const int64_t fixed = sa_overlaps_ws_bytes(n, 0);
+    // the text-sized part must fit before the read count is known
+    const int64_t fixed = sa_overlaps_ws_bytes(n, 1, 0);
     if (ws_needed_h) *ws_needed_h = fixed;
     if (ws_bytes < fixed) return fail(SA_ERR_NOMEM, "sa_overlaps: workspace too small");
     Tune t;
     resolve_tuning(nullptr, &t);
     hipStream_t s = stream;
-    Carver c(ws, ws_bytes);
     OvlFixed F;
-    carve_fixed(c, n, &F);
+    {
+        Carver c0(ws, ws_bytes);
+        carve_fixed(c0, n, 1, &F);  // pack area and counters only; read arrays carved below
+    }
     SA_TRY(launch_fill_u32(F.ctr, 64, 0, s));
     SA_TRY(launch_pack(text, n, F.packed, F.sepmask, F.wordcnt, F.ctr, s));
     const int64_t nw = (n + 31) / 32;
     SA_TRY(launch_scan_u32_i32(F.wordcnt, F.sepcnt, nw, reinterpret_cast<int32_t *>(F.ctr + 2),
                                F.lbflags, F.tick, F.ctr, s));
-    SA_TRY(launch_read_ends(F.sepmask, F.sepcnt, n, F.read_end, s));
     uint32_t host[4];
     SA_HIP(hipMemcpyAsync(host, F.ctr, 16, hipMemcpyDeviceToHost, s));
     SA_HIP(hipStreamSynchronize(s));
@@ -201,6 +206,14 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     if (host[0]) return fail(SA_ERR_HIP, "device consistency check failed");
     const int64_t m = int32_t(host[2]);
     if (m < 1 || m > n) return fail(SA_ERR_HIP, "sa_overlaps: bad read count");
+    {
+        const int64_t need_m = sa_overlaps_ws_bytes(n, m, 0);
+        if (ws_needed_h) *ws_needed_h = need_m;
+        if (ws_bytes < need_m) return fail(SA_ERR_NOMEM, "sa_overlaps: workspace too small for the reads");
+    }
+    Carver c(ws, ws_bytes);
+    carve_fixed(c, n, m, &F);  // same text-sized part; read arrays now sized by m
+    SA_TRY(launch_read_ends(F.sepmask, F.sepcnt, n, F.read_end, s));
 
     // count candidates per read, then scan to offsets
     const unsigned rgrid = unsigned((m + 255) / 256);
@@ -221,8 +234,8 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     SA_HIP(hipStreamSynchronize(s));
     timing_flush();
     if (e) return fail(SA_ERR_HIP, "sa_overlaps: device consistency check failed (code " + std::to_string(e) + ")");
-    if (r >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_overlaps: more than 2^30 candidate matches");
-    const int64_t need = sa_overlaps_ws_bytes(n, r);
+    if (r >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_overlaps: more than 2^31-2 candidate matches");
+    const int64_t need = sa_overlaps_ws_bytes(n, m, r);
     if (ws_needed_h) *ws_needed_h = need;
     if (ws_bytes < need) return fail(SA_ERR_NOMEM, "sa_overlaps: workspace too small for " + std::to_string(r) + " candidates");
     if (r == 0) {
@@ -245,8 +258,9 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     const int abits = bits_for_u(m - 1);
     if (abits > 0) {
         SA_TRY(sort_prepare(H.sb, r, abits, t, s));
-        SA_TRY(launch_hist(H.sb, 0, r, 32, abits, t, s));
-        SA_TRY(sort_run(H.sb, 0, r, 32, abits, t, s, &cur));
+        int nparts = 0;
+        SA_TRY(launch_hist(H.sb, 0, r, 32, abits, t, s, &nparts));
+        SA_TRY(sort_run(H.sb, 0, nullptr, r, 32, abits, t, nparts, s, &cur));
     }
     const unsigned hgrid = unsigned((r + 255) / 256);
     hipLaunchKernelGGL(k_run_heads, dim3(hgrid), dim3(256), 0, s, H.sb.keys[cur], uint32_t(r), H.first);

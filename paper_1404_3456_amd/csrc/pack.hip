@@ -247,7 +247,7 @@ extern "C" int sa_pack(const uint8_t *text, int64_t n, uint32_t *packed, uint32_
                        int64_t ws_bytes, hipStream_t stream) {
     if (!text || !packed || !sepmask || !m_h || !ws) return fail(SA_ERR_INVALID, "sa_pack: NULL pointer");
     if (n < 1) return fail(SA_ERR_INVALID, "sa_pack: n must be >= 1");
-    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_pack: n >= 2^30");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_pack: n >= 2^31-2");
     if (ws_bytes < sa_pack_ws_bytes(n)) return fail(SA_ERR_NOMEM, "sa_pack: workspace too small");
     Carver c(ws, ws_bytes);
     uint32_t *wordcnt = c.take<uint32_t>(sepmask_words(n));

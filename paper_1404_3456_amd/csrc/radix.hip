@@ -44,7 +44,7 @@ void carve_sort(Carver &c, int64_t n, int bits, const Tune &t, SortBufs *b, bool
         b->vals[0] = c.take<uint32_t>(n);
         b->vals[1] = c.take<uint32_t>(n);
     }
-    b->hist = c.take<uint32_t>(int64_t(P) * t.radix());
+    b->hist = c.take<uint32_t>(int64_t(kHistParts) * P * t.radix());
     b->gbase = c.take<uint32_t>(int64_t(P) * t.radix());
     b->flags = c.take<uint32_t>(sort_flag_words(n, bits, t) > 0 ? sort_flag_words(n, bits, t) : 1);
     b->tickets = c.take<uint32_t>(64);
@@ -53,7 +53,6 @@ void carve_sort(Carver &c, int64_t n, int bits, const Tune &t, SortBufs *b, bool
 int sort_prepare(const SortBufs &b, int64_t n, int bits, const Tune &t, hipStream_t s) {
     const int P = sort_passes(bits, t);
     if (P == 0) return SA_OK;
-    SA_TRY(launch_fill_u32(b.hist, int64_t(P) * t.radix(), 0, s));
     SA_TRY(launch_fill_u32(b.flags, sort_flag_words(n, bits, t), 0, s));
     SA_TRY(launch_fill_u32(b.tickets, 64, 0, s));
     return SA_OK;
@@ -72,13 +71,12 @@ __device__ __forceinline__ void hist_add(uint32_t *s_h, uint64_t f, int passes) 
         atomicAdd(&s_h[p * R + uint32_t((f >> (p * D)) & (R - 1))], 1u);
 }
 
+// Each workgroup stores its whole LDS histogram as one partial (plain stores, no atomics).
 template <int D>
-__device__ __forceinline__ void hist_flush(const uint32_t *s_h, uint32_t *hist, int passes) {
+__device__ __forceinline__ void hist_flush(const uint32_t *s_h, uint32_t *part, int passes) {
     constexpr int R = 1 << D;
-    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) {
-        uint32_t v = s_h[i];
-        if (v) atomicAdd(&hist[i], v);
-    }
+    uint32_t *dst = part + size_t(blockIdx.x) * passes * R;
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) dst[i] = s_h[i];
 }
 
 template <int D>
@@ -96,20 +94,28 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t *__restrict__ keys,
     hist_flush<D>(s_h, hist, passes);
 }
 
-// Exclusive scan of each pass's R digit counts (one workgroup per pass).
+// Sum the partial histograms of one pass and scan them into exclusive digit bases (one
+// workgroup per pass).
 template <int D>
-__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ hist,
-                                                   uint32_t *__restrict__ gbase) {
+__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ part, int nparts,
+                                                   int passes, uint32_t *__restrict__ gbase) {
     constexpr int R = 1 << D;
     constexpr int PER = (R + 255) / 256;
     __shared__ uint32_t s_w[4];
-    const uint32_t *h = hist + blockIdx.x * R;
+    __shared__ uint32_t s_sum[R];
+    for (int d = threadIdx.x; d < R; d += 256) {
+        uint32_t acc = 0;
+        const uint32_t *src = part + size_t(blockIdx.x) * R + d;
+        for (int w = 0; w < nparts; ++w) acc += src[size_t(w) * passes * R];
+        s_sum[d] = acc;
+    }
+    __syncthreads();
     uint32_t *g = gbase + blockIdx.x * R;
     uint32_t v[PER], sum = 0;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         int d = threadIdx.x * PER + j;
-        v[j] = d < R ? h[d] : 0;
+        v[j] = d < R ? s_sum[d] : 0;
         sum += v[j];
     }
     uint32_t total;
@@ -123,15 +129,16 @@ __global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ 
 }
 
 static unsigned hist_grid(int64_t n) {
-    int64_t b = (n + 2047) / 2048;
-    if (b > 2048) b = 2048;
+    int64_t b = (n + 4095) / 4096;
+    if (b > kHistParts) b = kHistParts;
     if (b < 1) b = 1;
     return unsigned(b);
 }
 
 int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
-                hipStream_t s) {
+                hipStream_t s, int *nparts) {
     const int P = sort_passes(bits, t);
+    *nparts = int(hist_grid(n));
     if (P == 0 || n == 0) return SA_OK;
     size_t lds = size_t(P) * t.radix() * 4;
     switch (t.dbits) {
@@ -145,11 +152,16 @@ int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, con
 }
 
 // ---- one LSD pass ---------------------------------------------------------------------------
+// One tile per workgroup, tiles numbered by ticket.  The grid covers an upper bound on the
+// item count; the count itself is read from device memory when `count_dev` is given (so the
+// same launch can be recorded in a graph and replayed with whatever count an earlier kernel
+// produced; surplus workgroups exit at once), otherwise it is `n_host`.
 template <int D, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__ kin,
                                                     const uint32_t *__restrict__ vin,
                                                     uint64_t *__restrict__ kout,
-                                                    uint32_t *__restrict__ vout, uint32_t n,
+                                                    uint32_t *__restrict__ vout,
+                                                    const uint32_t *count_dev, uint32_t n_host,
                                                     uint32_t shift, uint32_t dmask,
                                                     const uint32_t *__restrict__ gbase,
                                                     uint32_t *flags, uint32_t *tick,
@@ -168,178 +180,195 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
     __shared__ uint64_t s_stage[TILE]; // tile in digit order (keys, then values)
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    if (tid == 0) s_tile = ticket(tick);
-    for (int i = tid; i < W * R; i += BLOCK) s_wcnt[i] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t tbase = tile * TILE;
-    const uint32_t wbase = tbase + wave * (ITEMS * kWave);
+    const uint32_t n = count_dev ? *count_dev : n_host;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
 
-    uint64_t key[ITEMS];
-    uint32_t val[ITEMS];
-    uint32_t pos[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        uint32_t idx = wbase + k * kWave + lane;
-        if (idx < n) {
-            key[k] = kin[idx];
-            val[k] = vin[idx];
-        } else {
-            key[k] = 0;
-            val[k] = 0;
-        }
-    }
+    {
+        if (tid == 0) s_tile = ticket(tick);
+        for (int i = tid; i < W * R; i += BLOCK) s_wcnt[i] = 0;
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) return;
+        const uint32_t tbase = tile * TILE;
+        const uint32_t wbase = tbase + wave * (ITEMS * kWave);
 
-    // Stable rank of every item among the items of its wave with the same digit: items are
-    // taken in index order (k-major, lane-minor), the running count per digit kept in LDS.
+        uint64_t key[ITEMS];
+        uint32_t val[ITEMS];
+        uint32_t pos[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t idx = wbase + k * kWave + lane;
-        const bool valid = idx < n;
-        const uint32_t dg = valid ? (uint32_t(key[k] >> shift) & dmask) : 0u;
-        uint64_t m = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            const bool bit = (dg >> b) & 1u;
-            const uint64_t bb = ballot(bit);
-            m &= bit ? bb : ~bb;
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t idx = wbase + k * kWave + lane;
+            key[k] = idx < n ? kin[idx] : 0;
+            val[k] = idx < n ? vin[idx] : 0;
         }
-        if (valid) {
-            const uint64_t lt = m & lanemask_lt();
-            const uint32_t c0 = s_wcnt[wave * R + dg];
-            pos[k] = c0 + uint32_t(popc64(lt));
-            if (lt == 0) s_wcnt[wave * R + dg] = Cnt(c0 + uint32_t(popc64(m)));
-        }
-        wave_sync();
-    }
-    __syncthreads();
 
-    // Per digit: exclusive prefix over waves, and the tile total.
-    uint32_t tot[DPT];
+        // Stable rank of every item among the items of its wave with the same digit: items
+        // are taken in index order (k-major, lane-minor), the running count per digit in LDS.
 #pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-        const int d = tid * DPT + j;
-        uint32_t run = 0;
-        if (d < R) {
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t idx = wbase + k * kWave + lane;
+            const bool valid = idx < n;
+            const uint32_t dg = valid ? (uint32_t(key[k] >> shift) & dmask) : 0u;
+            uint64_t m = ballot(valid);
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                uint32_t c = s_wcnt[w * R + d];
-                s_wcnt[w * R + d] = Cnt(run);
-                run += c;
+            for (int b = 0; b < D; ++b) {
+                const bool bit = (dg >> b) & 1u;
+                const uint64_t bb = ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            if (valid) {
+                const uint64_t lt = m & lanemask_lt();
+                const uint32_t c0 = s_wcnt[wave * R + dg];
+                pos[k] = c0 + uint32_t(popc64(lt));
+                if (lt == 0) s_wcnt[wave * R + dg] = Cnt(c0 + uint32_t(popc64(m)));
+            }
+            wave_sync();
+        }
+        __syncthreads();
+
+        // Per digit: exclusive prefix over waves, and the tile total.
+        uint32_t tot[DPT];
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            uint32_t run = 0;
+            if (d < R) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    uint32_t c = s_wcnt[w * R + d];
+                    s_wcnt[w * R + d] = Cnt(run);
+                    run += c;
+                }
+            }
+            tot[j] = run;
+        }
+        // Publish this tile's counts before looking back, so later tiles can proceed.
+        uint32_t *myflags = flags + size_t(tile) * R;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            if (d < R) st_agent(myflags + d, lb32_word(tile == 0, tot[j]));
+        }
+        uint32_t tsum = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) tsum += tot[j];
+        uint32_t tile_total;
+        uint32_t run = block_excl_sum<BLOCK>(tsum, s_scan, &tile_total);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            if (d < R) {
+                uint32_t ex = 0;
+                if (tile > 0) {
+                    ex = lookback_digit(flags, int(tile), R, d, err);
+                    st_agent(myflags + d, lb32_word(true, ex + tot[j]));
+                }
+                s_lstart[d] = run;
+                s_gofs[d] = gbase[d] + ex - run;
+                run += tot[j];
             }
         }
-        tot[j] = run;
-    }
-    // Publish this tile's counts before looking back, so later tiles can proceed.
-    uint32_t *myflags = flags + size_t(tile) * R;
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-        const int d = tid * DPT + j;
-        if (d < R) st_agent(myflags + d, (tile == 0 ? kLb32Inc : kLb32Agg) | tot[j]);
-    }
-    uint32_t tsum = 0;
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) tsum += tot[j];
-    uint32_t tile_total;
-    uint32_t run = block_excl_sum<BLOCK>(tsum, s_scan, &tile_total);
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) {
-        const int d = tid * DPT + j;
-        if (d < R) {
-            uint32_t ex = 0;
-            if (tile > 0) {
-                ex = lookback_digit(flags, int(tile), R, d, err);
-                st_agent(myflags + d, kLb32Inc | (ex + tot[j]));
-            }
-            s_lstart[d] = run;
-            s_gofs[d] = gbase[d] + ex - run;
-            run += tot[j];
-        }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // Stage keys in digit order.
+        // Stage keys in digit order.
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t idx = wbase + k * kWave + lane;
-        if (idx < n) {
-            const uint32_t dg = uint32_t(key[k] >> shift) & dmask;
-            const uint32_t lp = s_lstart[dg] + uint32_t(s_wcnt[wave * R + dg]) + pos[k];
-            s_stage[lp] = key[k];
-            pos[k] = lp;
-        }
-    }
-    __syncthreads();
-    const uint32_t tcount = (n - tbase) < uint32_t(TILE) ? (n - tbase) : uint32_t(TILE);
-    uint32_t opos[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t lp = j * BLOCK + tid;
-        if (lp < tcount) {
-            const uint64_t kk = s_stage[lp];
-            const uint32_t dg = uint32_t(kk >> shift) & dmask;
-            uint32_t o = lp + s_gofs[dg];
-            if (o >= n) {  // only an inconsistent histogram can get here
-                raise_err(err, kErrRange);
-                o = 0xffffffffu;
-            } else {
-                kout[o] = kk;
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t idx = wbase + k * kWave + lane;
+            if (idx < n) {
+                const uint32_t dg = uint32_t(key[k] >> shift) & dmask;
+                const uint32_t lp = s_lstart[dg] + uint32_t(s_wcnt[wave * R + dg]) + pos[k];
+                s_stage[lp] = key[k];
+                pos[k] = lp;
             }
-            opos[j] = o;
+        }
+        __syncthreads();
+        const uint32_t tcount = (n - tbase) < uint32_t(TILE) ? (n - tbase) : uint32_t(TILE);
+        uint32_t opos[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t lp = j * BLOCK + tid;
+            opos[j] = 0xffffffffu;
+            if (lp < tcount) {
+                const uint64_t kk = s_stage[lp];
+                const uint32_t dg = uint32_t(kk >> shift) & dmask;
+                const uint32_t o = lp + s_gofs[dg];
+                if (o >= n) {
+                    raise_err(err, kErrRange);  // only an inconsistent histogram gets here
+                } else {
+                    kout[o] = kk;
+                    opos[j] = o;
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t *s_stage32 = reinterpret_cast<uint32_t *>(s_stage);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t idx = wbase + k * kWave + lane;
+            if (idx < n) s_stage32[pos[k]] = val[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t lp = j * BLOCK + tid;
+            if (lp < tcount && opos[j] != 0xffffffffu) vout[opos[j]] = s_stage32[lp];
         }
     }
-    __syncthreads();
-    uint32_t *s_stage32 = reinterpret_cast<uint32_t *>(s_stage);
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t idx = wbase + k * kWave + lane;
-        if (idx < n) s_stage32[pos[k]] = val[k];
+}
+
+static int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t lp = j * BLOCK + tid;
-        if (lp < tcount && opos[j] != 0xffffffffu) vout[opos[j]] = s_stage32[lp];
-    }
+    return cus;
 }
 
 template <int D, int BLOCK, int ITEMS>
-static void launch_pass_t(dim3 grid, hipStream_t s, const uint64_t *kin, const uint32_t *vin,
-                          uint64_t *kout, uint32_t *vout, uint32_t n, uint32_t shift,
-                          uint32_t dmask, const uint32_t *gbase, uint32_t *flags, uint32_t *tick,
-                          uint32_t *err) {
-    hipLaunchKernelGGL((k_onesweep<D, BLOCK, ITEMS>), grid, dim3(BLOCK), 0, s, kin, vin, kout,
-                       vout, n, shift, dmask, gbase, flags, tick, err);
-}
-
-template <int D>
-static int launch_pass_d(const Tune &t, dim3 grid, hipStream_t s, const uint64_t *kin,
-                         const uint32_t *vin, uint64_t *kout, uint32_t *vout, uint32_t n,
-                         uint32_t shift, uint32_t dmask, const uint32_t *gbase, uint32_t *flags,
-                         uint32_t *tick, uint32_t *err) {
-    if (t.block == 256 && t.items == 8)
-        launch_pass_t<D, 256, 8>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
-    else if (t.block == 256 && t.items == 16)
-        launch_pass_t<D, 256, 16>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
-    else if (t.block == 512 && t.items == 8)
-        launch_pass_t<D, 512, 8>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
-    else if (t.block == 512 && t.items == 16)
-        launch_pass_t<D, 512, 16>(grid, s, kin, vin, kout, vout, n, shift, dmask, gbase, flags, tick, err);
-    else
-        return fail(SA_ERR_INVALID, "unsupported tile shape");
+static int launch_pass_t(int64_t n_max, hipStream_t s, const uint64_t *kin, const uint32_t *vin,
+                         uint64_t *kout, uint32_t *vout, const uint32_t *count_dev,
+                         uint32_t n_host, uint32_t shift, uint32_t dmask, const uint32_t *gbase,
+                         uint32_t *flags, uint32_t *tick, uint32_t *err) {
+    constexpr int TILE = BLOCK * ITEMS;
+    int64_t grid = (n_max + TILE - 1) / TILE;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_onesweep<D, BLOCK, ITEMS>), dim3(unsigned(grid)), dim3(BLOCK), 0, s, kin,
+                       vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    SA_HIP(hipGetLastError());
     return SA_OK;
 }
 
-int sort_run(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const Tune &t,
-             hipStream_t s, int *cur_out) {
+template <int D>
+static int launch_pass_d(const Tune &t, int64_t n_max, hipStream_t s, const uint64_t *kin,
+                         const uint32_t *vin, uint64_t *kout, uint32_t *vout,
+                         const uint32_t *count_dev, uint32_t n_host, uint32_t shift,
+                         uint32_t dmask, const uint32_t *gbase, uint32_t *flags, uint32_t *tick,
+                         uint32_t *err) {
+    if (t.block == 256 && t.items == 8)
+        return launch_pass_t<D, 256, 8>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    if (t.block == 256 && t.items == 16)
+        return launch_pass_t<D, 256, 16>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    if (t.block == 512 && t.items == 8)
+        return launch_pass_t<D, 512, 8>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    if (t.block == 512 && t.items == 16)
+        return launch_pass_t<D, 512, 16>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    return fail(SA_ERR_INVALID, "unsupported tile shape");
+}
+
+int sort_run(const SortBufs &b, int cur, const uint32_t *count_dev, int64_t n, int bit_lo,
+             int bits, const Tune &t, int nparts, hipStream_t s, int *cur_out) {
     const int P = sort_passes(bits, t);
     *cur_out = cur;
     if (P == 0 || n <= 1) return SA_OK;
     const int R = t.radix();
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_hist_scan<4>, dim3(P), dim3(256), 0, s, b.hist, b.gbase); break;
-        case 8: hipLaunchKernelGGL(k_hist_scan<8>, dim3(P), dim3(256), 0, s, b.hist, b.gbase); break;
-        case 11: hipLaunchKernelGGL(k_hist_scan<11>, dim3(P), dim3(256), 0, s, b.hist, b.gbase); break;
+        case 4: hipLaunchKernelGGL(k_hist_scan<4>, dim3(P), dim3(256), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 8: hipLaunchKernelGGL(k_hist_scan<8>, dim3(P), dim3(256), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 11: hipLaunchKernelGGL(k_hist_scan<11>, dim3(P), dim3(256), 0, s, b.hist, nparts, P, b.gbase); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     SA_HIP(hipGetLastError());
@@ -351,17 +380,15 @@ int sort_run(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const 
         const uint32_t dmask = (1u << width) - 1u;
         TimedScope ts("radix_pass", double(n) * 24.0, s);
         int rc = SA_OK;
-        const dim3 grid{unsigned(tiles), 1u, 1u};
         uint32_t *fl = b.flags + size_t(p) * tiles * R;
         switch (t.dbits) {
-            case 4: rc = launch_pass_d<4>(t, grid, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
-            case 8: rc = launch_pass_d<8>(t, grid, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
-            case 11: rc = launch_pass_d<11>(t, grid, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            case 4: rc = launch_pass_d<4>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            case 8: rc = launch_pass_d<8>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            case 11: rc = launch_pass_d<11>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
             default: rc = fail(SA_ERR_INVALID, "unsupported digit width");
         }
         ts.finish();
         if (rc != SA_OK) return rc;
-        SA_HIP(hipGetLastError());
         cur ^= 1;
     }
     *cur_out = cur;
@@ -369,14 +396,17 @@ int sort_run(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, const 
 }
 
 // ---- key builders ---------------------------------------------------------------------------
-// First-round key of suffix p (h0 = kH0 bases): the 2-bit codes of T[p .. p+min(L_p, h0)),
+// First-round key of suffix p (prefix length h0 <= 29): the 2-bit codes of T[p .. p+min(L_p, h0)),
 // zero-padded to h0 bases, followed by min(L_p, h0) in 5 bits, where L_p is the distance from p
 // to the next separator.  Comparing two such keys as integers orders the suffixes by their
 // first h0 symbols with the separator below every base; keys equal with a length below h0
 // belong to suffixes that end at different separators at the same offset, whose order is
-// their position order (kept by the stable sort, since values are positions).
+// their position order (kept by the stable sort, since values are positions).  For a batch of
+// independent texts the text's index is placed above these bits, so every text's suffixes
+// form one contiguous block of the order.
 __device__ __forceinline__ uint64_t key0_of(const uint32_t *__restrict__ packed,
-                                            const uint32_t *__restrict__ sepmask, uint32_t p) {
+                                            const uint32_t *__restrict__ sepmask, uint32_t p,
+                                            uint32_t h0) {
     const uint32_t w = p >> 4, o = p & 15;
     uint64_t x = (uint64_t(packed[w]) << 32) | packed[w + 1];
     x <<= 2 * o;
@@ -384,16 +414,29 @@ __device__ __forceinline__ uint64_t key0_of(const uint32_t *__restrict__ packed,
     const uint32_t sw = p >> 5, so = p & 31;
     const uint64_t sm = ((uint64_t(sepmask[sw]) << 32) | sepmask[sw + 1]) << so;
     uint32_t L = sm ? uint32_t(__clzll((long long)sm)) : 64u;
-    if (L > uint32_t(kH0)) L = kH0;
-    uint64_t code = x >> (64 - 2 * kH0);
-    if (L < uint32_t(kH0)) code &= ~((uint64_t(1) << (2 * (kH0 - L))) - 1);
+    if (L > h0) L = h0;
+    uint64_t code = x >> (64 - 2 * h0);
+    if (L < h0) code &= ~((uint64_t(1) << (2 * (h0 - L))) - 1);
     return (code << 5) | L;
+}
+
+// Index of the text of a batch that holds position p: largest s with set_off[s] <= p.
+__device__ __forceinline__ uint32_t set_of(const int64_t *__restrict__ set_off, uint32_t n_sets,
+                                           uint32_t p) {
+    uint32_t lo = 0, hi = n_sets;  // invariant: set_off[lo] <= p < set_off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (set_off[mid] <= int64_t(p)) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_key0(const uint32_t *__restrict__ packed,
                                               const uint32_t *__restrict__ sepmask, uint32_t n,
-                                              uint64_t *__restrict__ keys,
+                                              uint32_t h0, const int64_t *__restrict__ set_off,
+                                              uint32_t n_sets, uint64_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals, int passes,
                                               uint32_t *__restrict__ hist) {
     constexpr int R = 1 << D;
@@ -401,8 +444,10 @@ __global__ __launch_bounds__(256) void k_key0(const uint32_t *__restrict__ packe
     for (int i = threadIdx.x; i < passes * R; i += blockDim.x) s_h[i] = 0;
     __syncthreads();
     const uint32_t stride = gridDim.x * blockDim.x;
+    const int set_shift = int(2 * h0 + 5);
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
-        const uint64_t k = key0_of(packed, sepmask, p);
+        uint64_t k = key0_of(packed, sepmask, p, h0);
+        if (set_off) k |= uint64_t(set_of(set_off, n_sets, p)) << set_shift;
         keys[p] = k;
         vals[p] = p;
         hist_add<D>(s_h, k, passes);
@@ -411,16 +456,18 @@ __global__ __launch_bounds__(256) void k_key0(const uint32_t *__restrict__ packe
     hist_flush<D>(s_h, hist, passes);
 }
 
-int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, const SortBufs &b,
-                int cur, const Tune &t, hipStream_t s) {
-    const int bits = 2 * kH0 + 5;
-    const int P = sort_passes(bits, t);
+int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int h0,
+                const int64_t *set_off_dev, int n_sets, int key_bits, const SortBufs &b, int cur,
+                const Tune &t, hipStream_t s, int *nparts) {
+    const int P = sort_passes(key_bits, t);
+    *nparts = int(hist_grid(n));
     size_t lds = size_t(P) * t.radix() * 4;
     TimedScope ts("keybuild", double(n) * (12.0 + 0.375), s);
+    const unsigned g = hist_grid(n);
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_key0<4>, dim3(hist_grid(n)), dim3(256), lds, s, packed, sepmask, uint32_t(n), b.keys[cur], b.vals[cur], P, b.hist); break;
-        case 8: hipLaunchKernelGGL(k_key0<8>, dim3(hist_grid(n)), dim3(256), lds, s, packed, sepmask, uint32_t(n), b.keys[cur], b.vals[cur], P, b.hist); break;
-        case 11: hipLaunchKernelGGL(k_key0<11>, dim3(hist_grid(n)), dim3(256), lds, s, packed, sepmask, uint32_t(n), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 4: hipLaunchKernelGGL(k_key0<4>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 8: hipLaunchKernelGGL(k_key0<8>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 11: hipLaunchKernelGGL(k_key0<11>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     ts.finish();
@@ -432,19 +479,21 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, cons
 // singleton, key = (rank[p] << rbits) | rank[p + h], value p, compacted in position order.
 // rank holds group labels (the suffix-array index of the group's first member) with kDone set
 // on singletons.  A suffix still in a non-singleton group after a round with prefix length h
-// has at least h symbols before its separator, so p + h stays inside the text.
+// has at least h symbols before its separator, so p + h stays inside the text.  The round's
+// active count and h are read from device memory (state[kStActive], state[kStH]); the number
+// of keys written goes to state[kStKeys].
 constexpr int kKbBlock = 256;
 constexpr int kKbItems = 8;
 constexpr int kKbTile = kKbBlock * kKbItems;
 
 template <int D>
 __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restrict__ rank,
-                                                       uint32_t n, uint32_t h, int rbits,
+                                                       uint32_t n, int rbits,
                                                        uint64_t *__restrict__ keys,
                                                        uint32_t *__restrict__ vals, int passes,
                                                        uint32_t *__restrict__ hist,
                                                        uint64_t *lbflags, uint32_t *tick,
-                                                       uint32_t *count_out, uint32_t *err) {
+                                                       uint32_t *state, uint32_t *err) {
     constexpr int R = 1 << D;
     constexpr int W = kKbBlock / kWave;
     extern __shared__ uint32_t s_h[];
@@ -452,66 +501,89 @@ __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restric
     __shared__ uint32_t s_chunk[kKbItems * W];
     __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    for (int i = tid; i < passes * R; i += kKbBlock) s_h[i] = 0;
-    if (tid == 0) s_tile = ticket(tick);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t tbase = tile * kKbTile;
-    uint32_t r[kKbItems];
-    uint64_t act[kKbItems];
-#pragma unroll
-    for (int j = 0; j < kKbItems; ++j) {
-        const uint32_t p = tbase + j * kKbBlock + tid;  // striped: wave covers 64 consecutive
-        r[j] = p < n ? rank[p] : kDone;
-        act[j] = ballot((r[j] & kDone) == 0);
-        if (lane == 0) s_chunk[j * W + wave] = uint32_t(popc64(act[j]));
-    }
-    __syncthreads();
-    if (wave == 0) {
-        // chunks are ordered (j, wave); <= 32 of them: one lane each
-        uint32_t c = lane < uint32_t(kKbItems * W) ? s_chunk[lane] : 0u;
-        uint32_t inc = wave_incl_scan<Sum32>(c);
-        uint32_t tile_total = __shfl(inc, kKbItems * W - 1);
-        if (lane < uint32_t(kKbItems * W)) s_chunk[lane] = inc - c;
-        uint64_t ex = lookback_tile<SumOp>(lbflags, int(tile), tile_total, err);
-        if (lane == 0) s_excl = ex;
-        if (lane == 0 && tbase + kKbTile >= n) *count_out = uint32_t(ex + tile_total);
-    }
-    __syncthreads();
     const uint64_t rmask = (uint64_t(1) << rbits) - 1;
+    const uint32_t active = state[kStActive];
+    const uint32_t h = state[kStH];
+    const uint32_t ntiles = active ? (n + kKbTile - 1) / kKbTile : 0u;
+    for (int i = tid; i < passes * R; i += kKbBlock) s_h[i] = 0;
+    // Persistent: tiles are taken in ticket order until none is left, so every tile a
+    // look-back waits on belongs to a workgroup that is already running.
+    while (true) {
+        __syncthreads();
+        if (tid == 0) s_tile = ticket(tick);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint32_t tbase = tile * kKbTile;
+        uint32_t r[kKbItems];
+        uint64_t act[kKbItems];
 #pragma unroll
-    for (int j = 0; j < kKbItems; ++j) {
-        const uint32_t p = tbase + j * kKbBlock + tid;
-        if ((r[j] & kDone) == 0) {
-            uint32_t r2 = 0;
-            if (p + h < n) r2 = rank[p + h] & kRankMask;
-            else raise_err(err, kErrRange);
-            const uint64_t k = ((uint64_t(r[j]) & rmask) << rbits) | (uint64_t(r2) & rmask);
-            const uint32_t o = uint32_t(s_excl) + s_chunk[j * W + wave] +
-                               uint32_t(popc64(act[j] & lanemask_lt()));
-            keys[o] = k;
-            vals[o] = p;
-            hist_add<D>(s_h, k, passes);
+        for (int j = 0; j < kKbItems; ++j) {
+            const uint32_t p = tbase + j * kKbBlock + tid;  // striped: a wave covers 64 in a row
+            r[j] = p < n ? rank[p] : kDone;
+            act[j] = ballot((r[j] & kDone) == 0);
+            if (lane == 0) s_chunk[j * W + wave] = uint32_t(popc64(act[j]));
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // chunks are ordered (j, wave); <= 64 of them: one lane each
+            uint32_t c = lane < uint32_t(kKbItems * W) ? s_chunk[lane] : 0u;
+            uint32_t inc = wave_incl_scan<Sum32>(c);
+            uint32_t tile_total = __shfl(inc, kKbItems * W - 1);
+            if (lane < uint32_t(kKbItems * W)) s_chunk[lane] = inc - c;
+            uint64_t ex = lookback_tile<SumOp>(lbflags, int(tile), tile_total, err);
+            if (lane == 0) s_excl = ex;
+            if (lane == 0 && tile == ntiles - 1) state[kStKeys] = uint32_t(ex + tile_total);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kKbItems; ++j) {
+            const uint32_t p = tbase + j * kKbBlock + tid;
+            if ((r[j] & kDone) == 0) {
+                uint32_t r2 = 0;
+                if (p + h < n) r2 = rank[p + h] & kRankMask;
+                else raise_err(err, kErrRange);
+                const uint64_t k = ((uint64_t(r[j]) & rmask) << rbits) | (uint64_t(r2) & rmask);
+                const uint32_t o = uint32_t(s_excl) + s_chunk[j * W + wave] +
+                                   uint32_t(popc64(act[j] & lanemask_lt()));
+                if (o < active) {
+                    keys[o] = k;
+                    vals[o] = p;
+                    hist_add<D>(s_h, k, passes);
+                } else {
+                    raise_err(err, kErrRange);
+                }
+            }
         }
     }
     __syncthreads();
     hist_flush<D>(s_h, hist, passes);
 }
 
-int launch_keys_doubling(const uint32_t *rank, int64_t n, int64_t h, int rbits,
-                         const SortBufs &b, int cur, uint64_t *lbflags, uint32_t *tick,
-                         uint32_t *count_out, const Tune &t, hipStream_t s) {
+int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, const SortBufs &b, int cur,
+                         uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
+                         hipStream_t s, int *nparts) {
     const int bits = 2 * rbits;
     const int P = sort_passes(bits, t);
     const int64_t tiles = (n + kKbTile - 1) / kKbTile;
+    static int per_cu = 0;
+    if (!per_cu) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_keys_dbl<8>, kKbBlock, size_t(P) * t.radix() * 4) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+    }
+    int64_t grid = int64_t(device_cus()) * per_cu;
+    if (grid > kHistParts) grid = kHistParts;
+    if (grid > tiles) grid = tiles;
+    if (grid < 1) grid = 1;
+    *nparts = int(grid);
     SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     size_t lds = size_t(P) * t.radix() * 4;
     TimedScope ts("keybuild", double(n) * 4.0, s);
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(tiles)), dim3(kKbBlock), lds, s, rank, uint32_t(n), uint32_t(h), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, count_out, b.err); break;
-        case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(tiles)), dim3(kKbBlock), lds, s, rank, uint32_t(n), uint32_t(h), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, count_out, b.err); break;
-        case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(tiles)), dim3(kKbBlock), lds, s, rank, uint32_t(n), uint32_t(h), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, count_out, b.err); break;
+        case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
+        case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
+        case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     ts.finish();
@@ -541,7 +613,7 @@ extern "C" int sa_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int32_t 
                              hipStream_t stream) {
     if (n < 0 || (n > 0 && (!keys || !vals || !ws)))
         return fail(SA_ERR_INVALID, "sa_sort_pairs: NULL pointer or negative n");
-    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_sort_pairs: n >= 2^30");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_sort_pairs: n >= 2^31-2");
     if (bit_lo < 0 || bit_hi > 64 || bit_lo >= bit_hi)
         return fail(SA_ERR_INVALID, "sa_sort_pairs: need 0 <= bit_lo < bit_hi <= 64");
     Tune t;
@@ -560,9 +632,10 @@ extern "C" int sa_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int32_t 
     if (!c.ok()) return fail(SA_ERR_NOMEM, "sa_sort_pairs: workspace too small");
     SA_TRY(launch_fill_u32(b.err, 1, 0, stream));
     SA_TRY(sort_prepare(b, n, bits, t, stream));
-    SA_TRY(launch_hist(b, 0, n, bit_lo, bits, t, stream));
+    int nparts = 0;
+    SA_TRY(launch_hist(b, 0, n, bit_lo, bits, t, stream, &nparts));
     int cur = 0;
-    SA_TRY(sort_run(b, 0, n, bit_lo, bits, t, stream, &cur));
+    SA_TRY(sort_run(b, 0, nullptr, n, bit_lo, bits, t, nparts, stream, &cur));
     if (cur == 1) {
         SA_HIP(hipMemcpyAsync(keys, b.keys[1], size_t(n) * 8, hipMemcpyDeviceToDevice, stream));
         SA_HIP(hipMemcpyAsync(vals, b.vals[1], size_t(n) * 4, hipMemcpyDeviceToDevice, stream));

@@ -1,18 +1,29 @@
 // sa_build.hip -- suffix array by prefix doubling over LSD radix sorts (Sec. IV: the suffix
 // array is the sorted array of all suffixes, built with a radix sort).
 //
-// Round 0 sorts every suffix by its first kH0 symbols (radix.hip, key0_of).  Each later round
+// Round 0 sorts every suffix by its first h0 symbols (radix.hip, key0_of).  Each later round
 // with prefix length h re-sorts only the suffixes whose group (set of suffixes equal on the
 // first h symbols) is not yet a singleton, by the rank pair (group of p, group of p+h), which
 // orders them by their first 2h symbols.  A round ends with the rank update below; the build
-// stops when no group has two members.  The early stop plays the role of the paper's "check
-// whether the output is sorted, and if not, continue with the next digit" (Sec. IV); because
+// stops when no group has two members.  The early stop plays the role of the paper's check
+// whether the output is already sorted before the next digit is processed (Sec. IV); because
 // the suffix array is unique it never changes the result.
 //
 // Group labels are suffix-array indices: the label of a group is the index of its first
 // member, so labels of groups that are already final never change and a round only touches
 // active suffixes.  When the build ends every group is a singleton and the label array is the
 // inverse suffix array.
+//
+// All round kernels read the active count and h from a small device-side state array, so a
+// doubling round can be recorded once as a hipGraph and replayed; once the active count is 0
+// every kernel of a replayed round returns at once.
+//
+// A batch of independent texts (sa_build_batched) is the same build over their
+// concatenation, with each text's index placed above the first-round key: every text's
+// suffixes then form one block of the order, labels of different texts never mix, and the
+// block of text s is exactly the suffix array of text s (in concatenated coordinates).
+#include <vector>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -24,102 +35,126 @@ constexpr int kRuTile = kRuBlock * kRuItems;
 
 // Rank update over the sorted active items (K, V) of a round, whose suffix-array slots are
 // S[0..A) (S == nullptr: identity, round 0).  For item i:
-//   head(i)   = i == 0, or K[i] != K[i-1], or (round 0 and K[i] encodes fewer than kH0 symbols:
+//   head(i)   = i == 0, or K[i] != K[i-1], or (round 0 and K[i] encodes fewer than h0 symbols:
 //               the suffix ended at its separator, which no other suffix shares);
 //   single(i) = head(i) and head(i+1) (i+1 == A counts as a head);
 //   label(i)  = S[g] where g is the last head at or before i.
 // Writes sa[S[i]] = V[i], rank[V[i]] = label | (single ? kDone : 0), and the slots of items
-// that are not singletons, compacted in order, to S_new; their count to *count_out.
+// that are not singletons, compacted in order, to S_new; their count to state[kStNext].
 __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     const uint64_t *__restrict__ K, const uint32_t *__restrict__ V, const uint32_t *__restrict__ S,
-    uint32_t A, uint32_t n, int round0, int32_t *__restrict__ sa, uint32_t *__restrict__ rank,
-    uint32_t *__restrict__ S_new, uint64_t *lbflags, uint32_t *tick, uint32_t *count_out,
+    uint32_t n, int round0, uint32_t h0, int32_t *__restrict__ sa, uint32_t *__restrict__ rank,
+    uint32_t *__restrict__ S_new, uint64_t *lbflags, uint32_t *tick, uint32_t *state,
     uint32_t *err) {
     __shared__ uint64_t s_k[kRuTile + 2];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_w[kRuBlock / kWave];
     __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    if (tid == 0) s_tile = ticket(tick);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t tbase = tile * kRuTile;
-    // keys of the tile plus one neighbour on each side (s_k[1 + i] = K[tbase + i])
-    for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock)
-        s_k[1 + i] = (tbase + i < A) ? K[tbase + i] : 0;
-    if (tid == 0) s_k[0] = tbase > 0 ? K[tbase - 1] : 0;
-    if (tid == 1) s_k[kRuTile + 1] = (tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
-    __syncthreads();
+    const uint32_t A = state[kStActive];
+    const uint32_t ntiles = (A + kRuTile - 1) / kRuTile;
+    while (true) {
+        __syncthreads();
+        if (tid == 0) s_tile = ticket(tick);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint32_t tbase = tile * kRuTile;
+        // keys of the tile plus one neighbour on each side (s_k[1 + i] = K[tbase + i])
+        for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock)
+            s_k[1 + i] = (tbase + i < A) ? K[tbase + i] : 0;
+        if (tid == 0) s_k[0] = tbase > 0 ? K[tbase - 1] : 0;
+        if (tid == 1) s_k[kRuTile + 1] = (tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
+        __syncthreads();
 
-    const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
-    bool head[kRuItems + 1];
+        const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
+        bool head[kRuItems + 1];
 #pragma unroll
-    for (int j = 0; j <= kRuItems; ++j) {
-        const uint32_t li = first + j;
-        const uint32_t i = tbase + li;
-        bool h = true;
-        if (i < A && i > 0) {
-            const uint64_t k = s_k[1 + li];
-            h = (k != s_k[li]) || (round0 && (k & 31u) < uint64_t(kH0));
-        }
-        head[j] = h;  // i >= A: counts as a head for the single() test of i-1
-    }
-    uint32_t cnt = 0, last = 0;
-#pragma unroll
-    for (int j = 0; j < kRuItems; ++j) {
-        const uint32_t i = tbase + first + j;
-        if (i < A) {
-            if (head[j]) last = i + 1;
-            if (!(head[j] && head[j + 1])) ++cnt;
-        }
-    }
-    // exclusive (count, last-head) scan over the workgroup, then over tiles
-    const uint64_t mine = (uint64_t(cnt) << 31) | last;
-    uint64_t inc = wave_incl_scan<CountLastOp>(mine);
-    if (lane == kWave - 1) s_w[wave] = inc;
-    __syncthreads();
-    uint64_t before = 0, tile_agg = 0;
-#pragma unroll
-    for (int w = 0; w < kRuBlock / kWave; ++w) {
-        if (uint32_t(w) < wave) before = CountLastOp::combine(before, s_w[w]);
-        tile_agg = CountLastOp::combine(tile_agg, s_w[w]);
-    }
-    uint64_t lane_excl = __shfl_up(inc, 1);
-    if (lane == 0) lane_excl = 0;
-    if (wave == 0) {
-        uint64_t ex = lookback_tile<CountLastOp>(lbflags, int(tile), tile_agg, err);
-        if (lane == 0) s_excl = ex;
-        if (lane == 0 && tbase + kRuTile >= A)
-            *count_out = uint32_t(CountLastOp::combine(ex, tile_agg) >> 31);
-    }
-    __syncthreads();
-    const uint64_t state = CountLastOp::combine(CountLastOp::combine(s_excl, before), lane_excl);
-    uint32_t out = uint32_t(state >> 31);
-    uint32_t g1 = uint32_t(state & CountLastOp::kLastMask);  // last head index + 1 (0: none)
-#pragma unroll
-    for (int j = 0; j < kRuItems; ++j) {
-        const uint32_t i = tbase + first + j;
-        if (i < A) {
-            if (head[j]) g1 = i + 1;
-            const bool single = head[j] && head[j + 1];
-            const uint32_t g = g1 - 1;  // i == 0 is always a head, so g1 >= 1
-            const uint32_t slot = S ? S[i] : i;
-            const uint32_t label = S ? S[g] : g;
-            const uint32_t v = V[i];
-            if (slot >= n || v >= n || label >= n) {  // inconsistent input: report, never write
-                raise_err(err, kErrRange);
-                continue;
+        for (int j = 0; j <= kRuItems; ++j) {
+            const uint32_t li = first + j;
+            const uint32_t i = tbase + li;
+            bool h = true;
+            if (i < A && i > 0) {
+                const uint64_t k = s_k[1 + li];
+                h = (k != s_k[li]) || (round0 && (k & 31u) < uint64_t(h0));
             }
-            sa[slot] = int32_t(v);
-            rank[v] = label | (single ? kDone : 0u);
-            if (!single) S_new[out++] = slot;
+            head[j] = h;  // i >= A: counts as a head for the single() test of i-1
+        }
+        uint32_t cnt = 0, last = 0;
+#pragma unroll
+        for (int j = 0; j < kRuItems; ++j) {
+            const uint32_t i = tbase + first + j;
+            if (i < A) {
+                if (head[j]) last = i + 1;
+                if (!(head[j] && head[j + 1])) ++cnt;
+            }
+        }
+        // exclusive (count, last-head) scan over the workgroup, then over tiles
+        const uint64_t mine = (uint64_t(cnt) << 31) | last;
+        uint64_t inc = wave_incl_scan<CountLastOp>(mine);
+        if (lane == kWave - 1) s_w[wave] = inc;
+        __syncthreads();
+        uint64_t before = 0, tile_agg = 0;
+#pragma unroll
+        for (int w = 0; w < kRuBlock / kWave; ++w) {
+            if (uint32_t(w) < wave) before = CountLastOp::combine(before, s_w[w]);
+            tile_agg = CountLastOp::combine(tile_agg, s_w[w]);
+        }
+        uint64_t lane_excl = __shfl_up(inc, 1);
+        if (lane == 0) lane_excl = 0;
+        if (wave == 0) {
+            uint64_t ex = lookback_tile<CountLastOp>(lbflags, int(tile), tile_agg, err);
+            if (lane == 0) s_excl = ex;
+            if (lane == 0 && tile == ntiles - 1)
+                state[kStNext] = uint32_t(CountLastOp::combine(ex, tile_agg) >> 31);
+        }
+        __syncthreads();
+        const uint64_t state_in = CountLastOp::combine(CountLastOp::combine(s_excl, before), lane_excl);
+        uint32_t out = uint32_t(state_in >> 31);
+        uint32_t g1 = uint32_t(state_in & CountLastOp::kLastMask);  // last head index + 1
+#pragma unroll
+        for (int j = 0; j < kRuItems; ++j) {
+            const uint32_t i = tbase + first + j;
+            if (i < A) {
+                if (head[j]) g1 = i + 1;
+                const bool single = head[j] && head[j + 1];
+                const uint32_t g = g1 - 1;  // i == 0 is always a head, so g1 >= 1
+                const uint32_t slot = S ? S[i] : i;
+                const uint32_t label = S ? S[g] : g;
+                const uint32_t v = V[i];
+                if (slot >= n || v >= n || label >= n) {  // inconsistent input: report only
+                    raise_err(err, kErrRange);
+                    continue;
+                }
+                sa[slot] = int32_t(v);
+                rank[v] = label | (single ? kDone : 0u);
+                if (!single) S_new[out++] = slot;
+            }
         }
     }
+}
+
+// Advances the round state after a rank update (one thread).
+__global__ void k_round_end(uint32_t *state, uint32_t h_first) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (state[kStActive] == 0) return;  // the round had nothing to do
+    const uint32_t rounds = state[kStRounds];
+    state[kStH] = rounds == 0 ? h_first : state[kStH] * 2u;
+    state[kStRounds] = rounds + 1;
+    state[kStActive] = state[kStNext];
 }
 
 __global__ __launch_bounds__(256) void k_strip(uint32_t *__restrict__ rank, uint32_t n) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) rank[i] &= kRankMask;
+}
+
+// Every text of a batch must be non-empty and end with a separator.
+__global__ void k_check_sets(const uint8_t *__restrict__ text, const int64_t *__restrict__ off,
+                             uint32_t n_sets, uint32_t *err) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sets) return;
+    if (off[s + 1] <= off[s] || text[off[s + 1] - 1] != '$') raise_err(err, kErrNoSepEnd);
 }
 
 static int bits_for(int64_t v) {  // bits needed to hold 0..v
@@ -135,11 +170,12 @@ struct BuildLayout {
     SortBufs sb;
     uint64_t *lbflags;
     uint32_t *tickets;
-    uint32_t *ctr;         // [0] err, [1] count (rank update), [2] count (key build)
+    uint32_t *state;       // kSt* words
+    int64_t *set_off;      // batched builds: [n_sets + 1]
 };
 
-static void carve_build(Carver &c, int64_t n, const Tune &t, BuildLayout *L) {
-    const int bits = 2 * kH0 + 5 > 2 * bits_for(n) ? 2 * kH0 + 5 : 2 * bits_for(n);
+static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLayout *L) {
+    const int bits = 63 > 2 * bits_for(n) ? 63 : 2 * bits_for(n);
     L->packed = c.take<uint32_t>(packed_words(n));
     L->sepmask = c.take<uint32_t>(sepmask_words(n));
     L->wordcnt = c.take<uint32_t>(sepmask_words(n));
@@ -150,37 +186,211 @@ static void carve_build(Carver &c, int64_t n, const Tune &t, BuildLayout *L) {
     const int64_t lbw = (n + kRuTile - 1) / kRuTile + (n + 2047) / 2048 + 16;
     L->lbflags = c.take<uint64_t>(lbw);
     L->tickets = c.take<uint32_t>(64);
-    L->ctr = c.take<uint32_t>(64);
+    L->state = c.take<uint32_t>(64);
+    L->set_off = c.take<int64_t>(n_sets + 1);
 }
 
-static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32_t *S, int64_t A,
-                              int64_t n, bool round0, int32_t *sa, uint32_t *rank, uint32_t *S_new,
-                              uint64_t *lbflags, uint32_t *tick, uint32_t *count_out,
-                              uint32_t *err, hipStream_t s) {
-    const int64_t tiles = (A + kRuTile - 1) / kRuTile;
-    SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
+static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32_t *S,
+                              int64_t a_bound, int64_t n, bool round0, int h0, int32_t *sa,
+                              uint32_t *rank, uint32_t *S_new, uint64_t *lbflags, uint32_t *tick,
+                              uint32_t *state, hipStream_t s) {
+    const int64_t tiles = (a_bound + kRuTile - 1) / kRuTile;
+    static int per_cu = 0;
+    if (!per_cu) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rank_update, kRuBlock, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t grid = int64_t(cus) * per_cu;
+    if (grid > tiles) grid = tiles;
+    if (grid < 1) grid = 1;
+    SA_TRY(launch_fill_u64(lbflags, tiles > 0 ? tiles : 1, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     // algorithmic bytes: read K (8) + V (4) + S (4 when present); write sa (4) + rank (4) +
     // S_new (4, upper bound)
-    TimedScope ts("rank_update", double(A) * (S ? 28.0 : 24.0), s);
-    hipLaunchKernelGGL(k_rank_update, dim3(unsigned(tiles)), dim3(kRuBlock), 0, s, K, V, S,
-                       uint32_t(A), uint32_t(n), int(round0), sa, rank, S_new, lbflags, tick, count_out, err);
+    TimedScope ts("rank_update", double(a_bound) * (S ? 28.0 : 24.0), s);
+    hipLaunchKernelGGL(k_rank_update, dim3(unsigned(grid)), dim3(kRuBlock), 0, s, K, V, S,
+                       uint32_t(n), int(round0), uint32_t(h0), sa, rank, S_new, lbflags, tick,
+                       state, state + kStErr);
     ts.finish();
     SA_HIP(hipGetLastError());
     return SA_OK;
 }
 
-static int read_ctr(const uint32_t *ctr, uint32_t host[4], hipStream_t s) {
-    SA_HIP(hipMemcpyAsync(host, ctr, 16, hipMemcpyDeviceToHost, s));
-    SA_HIP(hipStreamSynchronize(s));
-    timing_flush();
+static int check_err(uint32_t e) {
+    if (e & kErrAlphabet) return fail(SA_ERR_ALPHABET, "text holds a byte other than A, C, G, T, $");
+    if (e & kErrNoSepEnd) return fail(SA_ERR_INVALID, "every text must end with '$'");
+    if (e) return fail(SA_ERR_HIP, "device consistency check failed (code " + std::to_string(e) + ")");
     return SA_OK;
 }
 
-static int check_err(uint32_t e) {
-    if (e & kErrAlphabet) return fail(SA_ERR_ALPHABET, "text holds a byte other than A, C, G, T, $");
-    if (e & kErrNoSepEnd) return fail(SA_ERR_INVALID, "text must end with '$'");
-    if (e) return fail(SA_ERR_HIP, "device consistency check failed (code " + std::to_string(e) + ")");
+// One suffix-array build (plain: one text; batched: n_sets texts, set_off_h on the host).
+struct Build {
+    const uint8_t *text;
+    int64_t n;
+    int n_sets;          // 0: plain text
+    const int64_t *set_off_h;
+    int32_t *sa;
+    uint32_t *rank;
+    Tune t;
+    BuildLayout L;
+    hipStream_t s;
+    int h0 = kH0;
+    int key0_bits = 2 * kH0 + 5;
+    int rbits = 1;
+
+    int read_state(uint32_t host[8]) {
+        SA_HIP(hipMemcpyAsync(host, L.state, 32, hipMemcpyDeviceToHost, s));
+        SA_HIP(hipStreamSynchronize(s));
+        timing_flush();
+        return SA_OK;
+    }
+
+    int round0() {
+        SA_TRY(launch_fill_u32(L.state, 64, 0, s));
+        SA_TRY(launch_fill_u32(L.state + kStActive, 1, uint32_t(n), s));
+        SA_TRY(launch_pack(text, n, L.packed, L.sepmask, L.wordcnt, L.state + kStErr, s));
+        const int64_t *set_off_dev = nullptr;
+        if (n_sets > 0) {
+            SA_HIP(hipMemcpyAsync(L.set_off, set_off_h, size_t(n_sets + 1) * 8, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_check_sets, dim3(unsigned((n_sets + 255) / 256)), dim3(256), 0, s,
+                               text, L.set_off, uint32_t(n_sets), L.state + kStErr);
+            SA_HIP(hipGetLastError());
+            set_off_dev = L.set_off;
+        }
+        SA_TRY(sort_prepare(L.sb, n, key0_bits, t, s));
+        int nparts = 0;
+        SA_TRY(launch_key0(L.packed, L.sepmask, n, h0, set_off_dev, n_sets, key0_bits, L.sb, 0, t, s, &nparts));
+        int cur = 0;
+        SA_TRY(sort_run(L.sb, 0, nullptr, n, 0, key0_bits, t, nparts, s, &cur));
+        SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], nullptr, n, n, true, h0, sa, rank,
+                                  L.slots[0], L.lbflags, L.tickets, L.state, s));
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
+        SA_HIP(hipGetLastError());
+        return SA_OK;
+    }
+
+    // One doubling round reading its slots from slots[sl] and writing slots[sl ^ 1]; a_bound
+    // bounds the active count (grid and fill sizes).
+    int doubling_round(int sl, int64_t a_bound) {
+        const int bits = 2 * rbits;
+        SA_TRY(sort_prepare(L.sb, a_bound, bits, t, s));
+        int nparts = 0;
+        SA_TRY(launch_keys_doubling(rank, n, rbits, L.sb, 0, L.lbflags, L.tickets, L.state, t, s, &nparts));
+        int cur = 0;
+        SA_TRY(sort_run(L.sb, 0, L.state + kStActive, a_bound, 0, bits, t, nparts, s, &cur));
+        SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], L.slots[sl], a_bound, n, false, h0,
+                                  sa, rank, L.slots[sl ^ 1], L.lbflags, L.tickets, L.state, s));
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
+        SA_HIP(hipGetLastError());
+        return SA_OK;
+    }
+
+    int run(bool use_graph, int *rounds_out) {
+        rbits = bits_for(n - 1);
+        SA_TRY(round0());
+        uint32_t host[8];
+        SA_TRY(read_state(host));
+        SA_TRY(check_err(host[kStErr]));
+        int64_t A = host[kStActive];
+        int sl = 0;
+        if (use_graph && A > 0) {
+            // Record two rounds (the slot buffers alternate) once and replay until done.
+            const int64_t bound = A;
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            // Capture on a private stream (the caller's may be the legacy default stream,
+            // which cannot be captured); the graph is then launched on the caller's stream.
+            hipStream_t cap = nullptr;
+            SA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            const hipStream_t caller = s;
+            s = cap;
+            timing_pause(true);
+            hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            int rc = be == hipSuccess ? SA_OK : fail(SA_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(be));
+            if (rc == SA_OK) rc = doubling_round(0, bound);
+            if (rc == SA_OK) rc = doubling_round(1, bound);
+            hipError_t ce = be == hipSuccess ? hipStreamEndCapture(cap, &graph) : hipSuccess;
+            timing_pause(false);
+            s = caller;
+            hipStreamDestroy(cap);
+            if (rc != SA_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return rc;
+            }
+            SA_HIP(ce);
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            SA_HIP(ie);
+            int guard = 0;
+            while (A > 0) {
+                if (++guard > 40) {
+                    hipGraphExecDestroy(exec);
+                    return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
+                }
+                hipError_t le = hipGraphLaunch(exec, s);
+                if (le != hipSuccess) {
+                    hipGraphExecDestroy(exec);
+                    SA_HIP(le);
+                }
+                int rr = read_state(host);
+                if (rr != SA_OK) { hipGraphExecDestroy(exec); return rr; }
+                if (host[kStErr]) { hipGraphExecDestroy(exec); return check_err(host[kStErr]); }
+                A = host[kStActive];
+            }
+            SA_HIP(hipGraphExecDestroy(exec));
+        } else {
+            while (A > 0) {
+                if (host[kStRounds] > 40) return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
+                SA_TRY(doubling_round(sl, A));
+                SA_TRY(read_state(host));
+                SA_TRY(check_err(host[kStErr]));
+                if (int64_t(host[kStKeys]) != A) return fail(SA_ERR_HIP, "sa_build: active-suffix count mismatch");
+                A = host[kStActive];
+                sl ^= 1;
+            }
+        }
+        if (rounds_out) *rounds_out = int(host[kStRounds]);
+        return SA_OK;
+    }
+};
+
+static int build_common(const uint8_t *text, int64_t n, const int64_t *set_off_h, int32_t n_sets,
+                        int32_t *sa, int32_t *isa_or_null, void *ws, int64_t ws_bytes,
+                        const sa_tuning *tune, bool use_graph, int32_t *rounds_h,
+                        hipStream_t stream, int64_t need) {
+    Tune t;
+    SA_TRY(resolve_tuning(tune, &t));
+    if (ws_bytes < need)
+        return fail(SA_ERR_NOMEM, "workspace too small (need " + std::to_string(need) + " bytes)");
+    Build B;
+    B.text = text;
+    B.n = n;
+    B.n_sets = n_sets;
+    B.set_off_h = set_off_h;
+    B.sa = sa;
+    B.t = t;
+    B.s = stream;
+    Carver c(ws, ws_bytes);
+    carve_build(c, n, n_sets, t, &B.L);
+    B.L.sb.err = B.L.state + kStErr;
+    B.rank = isa_or_null ? reinterpret_cast<uint32_t *>(isa_or_null) : B.L.rank;
+    if (n_sets > 0) {
+        int sb = 0;
+        while ((int64_t(1) << sb) < n_sets) ++sb;
+        B.h0 = (63 - 5 - sb) / 2 < kH0 ? (63 - 5 - sb) / 2 : kH0;
+        if (B.h0 < 1) return fail(SA_ERR_INVALID, "too many texts in one batch");
+        B.key0_bits = 2 * B.h0 + 5 + sb;
+    }
+    int rounds = 0;
+    SA_TRY(B.run(use_graph, &rounds));
+    if (isa_or_null) {
+        unsigned grid = unsigned((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+        hipLaunchKernelGGL(k_strip, dim3(grid), dim3(256), 0, stream, B.rank, uint32_t(n));
+        SA_HIP(hipGetLastError());
+    }
+    if (rounds_h) *rounds_h = rounds;
     return SA_OK;
 }
 
@@ -193,7 +403,7 @@ extern "C" int64_t sa_build_ws_bytes(int64_t n, const sa_tuning *tune) {
     if (n < 1 || resolve_tuning(tune, &t) != SA_OK) return -1;
     Carver c(nullptr, INT64_MAX);
     BuildLayout L;
-    carve_build(c, n, t, &L);
+    carve_build(c, n, 0, t, &L);
     return c.off + 256;
 }
 
@@ -202,60 +412,36 @@ extern "C" int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *is
                         hipStream_t stream) {
     if (!text || !sa || !ws) return fail(SA_ERR_INVALID, "sa_build: NULL pointer");
     if (n < 1) return fail(SA_ERR_INVALID, "sa_build: n must be >= 1");
-    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_build: n >= 2^30");
-    Tune t;
-    SA_TRY(resolve_tuning(tune, &t));
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_build: n >= 2^31-2");
     const int64_t need = sa_build_ws_bytes(n, tune);
-    if (ws_bytes < need)
-        return fail(SA_ERR_NOMEM, "sa_build: workspace too small (need " + std::to_string(need) + " bytes)");
-    Carver c(ws, ws_bytes);
+    if (need < 0) return fail(SA_ERR_INVALID, "sa_build: bad tuning");
+    return build_common(text, n, nullptr, 0, sa, isa_or_null, ws, ws_bytes, tune, false, rounds_h,
+                        stream, need);
+}
+
+extern "C" int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const sa_tuning *tune) {
+    Tune t;
+    if (n < 1 || n_sets < 1 || resolve_tuning(tune, &t) != SA_OK) return -1;
+    Carver c(nullptr, INT64_MAX);
     BuildLayout L;
-    carve_build(c, n, t, &L);
-    L.sb.err = L.ctr;
-    uint32_t *rank = isa_or_null ? reinterpret_cast<uint32_t *>(isa_or_null) : L.rank;
-    hipStream_t s = stream;
+    carve_build(c, n, n_sets, t, &L);
+    return c.off + 256;
+}
 
-    SA_TRY(launch_fill_u32(L.ctr, 64, 0, s));
-    SA_TRY(launch_pack(text, n, L.packed, L.sepmask, L.wordcnt, L.ctr, s));
-
-    // round 0: first kH0 symbols
-    const int bits0 = 2 * kH0 + 5;
-    SA_TRY(sort_prepare(L.sb, n, bits0, t, s));
-    SA_TRY(launch_key0(L.packed, L.sepmask, n, L.sb, 0, t, s));
-    int cur = 0;
-    SA_TRY(sort_run(L.sb, 0, n, 0, bits0, t, s, &cur));
-    SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], nullptr, n, n, true, sa, rank,
-                              L.slots[0], L.lbflags, L.tickets, L.ctr + 1, L.ctr, s));
-    uint32_t host[4];
-    SA_TRY(read_ctr(L.ctr, host, s));
-    SA_TRY(check_err(host[0]));
-    int64_t A = host[1];
-    int rounds = 1;
-    int sl = 0;
-    const int rbits = bits_for(n - 1);
-    int64_t h = kH0;
-    while (A > 0) {
-        if (h > 2 * n) return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
-        const int bits = 2 * rbits;
-        SA_TRY(sort_prepare(L.sb, A, bits, t, s));
-        SA_TRY(launch_keys_doubling(rank, n, h, rbits, L.sb, 0, L.lbflags, L.tickets, L.ctr + 2, t, s));
-        SA_TRY(sort_run(L.sb, 0, A, 0, bits, t, s, &cur));
-        SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], L.slots[sl], A, n, false, sa, rank,
-                                  L.slots[sl ^ 1], L.lbflags, L.tickets, L.ctr + 1, L.ctr, s));
-        SA_TRY(read_ctr(L.ctr, host, s));
-        SA_TRY(check_err(host[0]));
-        if (int64_t(host[2]) != A)
-            return fail(SA_ERR_HIP, "sa_build: active-suffix count mismatch");
-        A = host[1];
-        sl ^= 1;
-        h *= 2;
-        ++rounds;
-    }
-    if (isa_or_null) {
-        unsigned grid = unsigned((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-        hipLaunchKernelGGL(k_strip, dim3(grid), dim3(256), 0, s, rank, uint32_t(n));
-        SA_HIP(hipGetLastError());
-    }
-    if (rounds_h) *rounds_h = rounds;
-    return SA_OK;
+extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h,
+                                int32_t n_sets, int32_t *sa, int32_t *isa_or_null, void *ws,
+                                int64_t ws_bytes, const sa_tuning *tune, int32_t use_graph,
+                                int32_t *rounds_h, hipStream_t stream) {
+    if (!text || !sa || !ws || !set_off_h) return fail(SA_ERR_INVALID, "sa_build_batched: NULL pointer");
+    if (n < 1 || n_sets < 1) return fail(SA_ERR_INVALID, "sa_build_batched: need n >= 1 and n_sets >= 1");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_build_batched: n >= 2^31-2");
+    if (set_off_h[0] != 0 || set_off_h[n_sets] != n)
+        return fail(SA_ERR_INVALID, "sa_build_batched: offsets must start at 0 and end at n");
+    for (int32_t i = 0; i < n_sets; ++i)
+        if (set_off_h[i + 1] <= set_off_h[i])
+            return fail(SA_ERR_INVALID, "sa_build_batched: every text must be non-empty");
+    const int64_t need = sa_build_batched_ws_bytes(n, n_sets, tune);
+    if (need < 0) return fail(SA_ERR_INVALID, "sa_build_batched: bad tuning");
+    return build_common(text, n, set_off_h, n_sets, sa, isa_or_null, ws, ws_bytes, tune,
+                        use_graph != 0, rounds_h, stream, need);
 }

@@ -52,7 +52,7 @@ def test_version_and_workspace_sizes():
     assert _abi.sa_build_ws_bytes(0) == -1
     assert _abi.sa_build_ws_bytes(10, {"digit_bits": 5}) == -1
     assert _abi.sa_lcp_ws_bytes(100) > 0
-    assert _abi.sa_overlaps_ws_bytes(100, 0) < _abi.sa_overlaps_ws_bytes(100, 1000)
+    assert _abi.sa_overlaps_ws_bytes(100, 1, 0) < _abi.sa_overlaps_ws_bytes(100, 10, 1000)
 
 
 def test_host_argument_checks_without_gpu():
@@ -62,7 +62,7 @@ def test_host_argument_checks_without_gpu():
     assert "NULL" in _abi.sa_last_error()
     dummy = P(16)
     assert lib.sa_build(dummy, 0, dummy, None, dummy, 1 << 20, None, None, None) == _abi.SA_ERR_INVALID
-    assert lib.sa_build(dummy, 1 << 30, dummy, None, dummy, 1 << 20, None, None, None) == _abi.SA_ERR_TOO_LARGE
+    assert lib.sa_build(dummy, (1 << 31) - 2, dummy, None, dummy, 1 << 20, None, None, None) == _abi.SA_ERR_TOO_LARGE
     assert lib.sa_build(dummy, 100, dummy, None, dummy, 16, None, None, None) == _abi.SA_ERR_NOMEM
     bad = _abi.Tuning(digit_bits=7).c()
     assert lib.sa_build(dummy, 100, dummy, None, dummy, 1 << 30, ctypes.byref(bad), None, None) == _abi.SA_ERR_INVALID

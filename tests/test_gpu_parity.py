@@ -213,3 +213,62 @@ def test_repeat_runs_identical(lib):
         again = run_all(lib, t, 20)
         for a, b in zip(first, again):
             assert np.array_equal(a, b)
+
+
+# ---- batched build: many independent texts in one set of launches ---------------------------
+
+def _batched_case(seed, n_sets, g_lo=200, g_hi=4000):
+    rng = np.random.default_rng(seed)
+    texts = []
+    for s in range(n_sets):
+        g = int(rng.integers(g_lo, g_hi))
+        m = int(rng.integers(1, 40))
+        L = int(rng.integers(5, min(120, g)))
+        texts.append(synth.genome_reads(seed * 1000 + s, g, m, L, err=0.01 * (s % 2),
+                                        alphabet_size=2 + s % 3))
+    off = np.concatenate([[0], np.cumsum([t.size for t in texts])]).astype(np.int64)
+    return texts, off, np.concatenate(texts)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("seed,n_sets", [(1, 1), (2, 7), (3, 64), (4, 300)])
+def test_batched_parity(lib, seed, n_sets, use_graph):
+    texts, off, cat = _batched_case(seed, n_sets)
+    t = dev(cat)
+    sa, isa = lib.sa_build_batched(t, off, use_graph=use_graph)
+    lcp = lib.sa_lcp(t, sa, isa)
+    ovl = lib.sa_overlaps(t, sa, isa, lcp, 4).cpu().numpy()
+    sa, isa, lcp = sa.cpu().numpy(), isa.cpu().numpy(), lcp.cpu().numpy()
+    assert np.array_equal(isa[sa], np.arange(cat.size))
+    reads_before = 0
+    rows = []
+    for s, txt in enumerate(texts):
+        lo, hi = off[s], off[s + 1]
+        want_sa = oracle.suffix_array(txt)
+        assert np.array_equal(sa[lo:hi] - lo, want_sa), f"set {s}"
+        assert np.array_equal(lcp[lo:hi], oracle.lcp_array(txt, want_sa)), f"set {s} lcp"
+        o = oracle.overlaps(txt, 4).astype(np.int64)
+        o[:, :2] += reads_before
+        rows.append(o)
+        reads_before += int((txt == ord("$")).sum())
+    want = np.concatenate(rows) if rows else np.zeros((0, 3))
+    assert np.array_equal(ovl.astype(np.int64), want)
+
+
+def test_batched_matches_plain_per_set(lib):
+    texts, off, cat = _batched_case(9, 20, 1000, 20000)
+    sa_b, _ = lib.sa_build_batched(dev(cat), off)
+    sa_b = sa_b.cpu().numpy()
+    for s, txt in enumerate(texts):
+        sa_p, _ = run_sa(lib, txt)
+        assert np.array_equal(sa_b[off[s]:off[s + 1]] - off[s], sa_p)
+
+
+def test_batched_rejects_bad_offsets(lib):
+    texts, off, cat = _batched_case(5, 3)
+    bad = off.copy()
+    bad[1] -= 1  # text 0 no longer ends with '$'
+    with pytest.raises(lib.SaasmError):
+        lib.sa_build_batched(dev(cat), bad)
+    with pytest.raises(lib.SaasmError):
+        lib.sa_build_batched(dev(cat), off[:-1])

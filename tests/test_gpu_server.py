@@ -1,0 +1,115 @@
+"""GPU tests of the job server: results identical alone and in a mix, bad jobs rejected with the
+server still running, an injected allocation failure fails only its batch."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1404_3456_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_1404_3456_amd as p
+    p.load()
+    return p
+
+
+def wait(srv, jid, timeout=120.0):
+    t0 = time.time()
+    while True:
+        r = srv.asm_poll(jid)
+        if r is not None:
+            return r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"job {jid}")
+        time.sleep(0.001)
+
+
+def host(r):
+    return (r["sa"].cpu().numpy(), r["isa"].cpu().numpy(), r["lcp"].cpu().numpy(),
+            r["ovl"].cpu().numpy())
+
+
+def jobs_pool(k, seed=3):
+    out = []
+    rng = np.random.default_rng(seed)
+    for j in range(k):
+        g = int(rng.integers(500, 30_000))
+        out.append(synth.genome_reads(seed * 100 + j, g, int(rng.integers(5, 200)),
+                                      int(rng.integers(30, min(300, g))), err=0.005))
+    return out
+
+
+@pytest.mark.parametrize("mode,workers", [(0, 1), (0, 3), (1, 1)])
+def test_server_results_match_oracle(pkg, mode, workers):
+    texts = jobs_pool(12)
+    with pkg.AsmServer(1 << 30, max_jobs_per_batch=8, workers=workers, mode=mode) as srv:
+        ids = [srv.asm_submit(t, 20) for t in texts]
+        for jid, t in zip(ids, texts):
+            r = wait(srv, jid)
+            assert r["status"] == 0
+            sa, isa, lcp, ovl = host(r)
+            want = oracle.suffix_array(t)
+            assert np.array_equal(sa, want)
+            assert np.array_equal(isa[sa], np.arange(t.size))
+            assert np.array_equal(lcp, oracle.lcp_array(t, want))
+            assert np.array_equal(ovl, oracle.overlaps(t, 20))
+            assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+            srv.asm_release(jid)
+        st = srv.asm_server_stats()
+        assert st["jobs_done"] == len(texts) and st["arena_used"] == 0
+
+
+def test_same_result_alone_and_in_mix(pkg):
+    texts = jobs_pool(20, seed=8)
+    probe = texts[7]
+    with pkg.AsmServer(1 << 30, max_jobs_per_batch=32, workers=2) as srv:
+        alone = srv.asm_submit(probe, 25)
+        ra = host(wait(srv, alone))
+        ids = [srv.asm_submit(t, 25) for t in texts]  # probe again, now inside a mix
+        rm = host(wait(srv, ids[7]))
+        for a, b in zip(ra, rm):
+            assert np.array_equal(a, b)
+        for jid in ids:
+            wait(srv, jid)
+        assert srv.asm_server_stats()["batches"] < 1 + len(texts)  # jobs were batched
+
+
+def test_bad_jobs_rejected_server_keeps_running(pkg):
+    with pkg.AsmServer(1 << 28, workers=1) as srv:
+        with pytest.raises(pkg.SaasmError) as e:
+            srv.asm_submit(np.frombuffer(b"ACGN$", dtype=np.uint8), 3)
+        assert e.value.code == pkg.SA_ERR_ALPHABET
+        with pytest.raises(pkg.SaasmError):
+            srv.asm_submit(np.frombuffer(b"ACGT", dtype=np.uint8), 3)
+        big = np.full(50_000_000, ord("A"), dtype=np.uint8)
+        big[-1] = ord("$")
+        with pytest.raises(pkg.SaasmError) as e:
+            srv.asm_submit(big, 3)  # over the 256 MiB budget
+        assert e.value.code == pkg.SA_ERR_NOMEM
+        t = jobs_pool(1)[0]
+        r = wait(srv, srv.asm_submit(t, 20))
+        assert r["status"] == 0
+        assert np.array_equal(host(r)[0], oracle.suffix_array(t))
+
+
+def test_injected_alloc_failure_fails_one_batch_only(pkg):
+    texts = jobs_pool(6, seed=11)
+    with pkg.AsmServer(1 << 30, max_jobs_per_batch=1, workers=1) as srv:
+        srv.fail_alloc_after(1)  # the next batch's first allocation fails
+        first = srv.asm_submit(texts[0], 20)
+        r0 = wait(srv, first)
+        assert r0["status"] == pkg.SA_ERR_NOMEM
+        ids = [srv.asm_submit(t, 20) for t in texts[1:]]
+        for jid, t in zip(ids, texts[1:]):
+            r = wait(srv, jid)
+            assert r["status"] == 0
+            assert np.array_equal(host(r)[0], oracle.suffix_array(t))
+            srv.asm_release(jid)
+        srv.asm_release(first)
+        assert srv.asm_server_stats()["arena_used"] == 0
