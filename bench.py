@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--max-total", type=int, default=0,
                     help="batched workload: stop adding sets once this many characters are drawn")
     ap.add_argument("--no-graph", action="store_true", help="batched workload: no hipGraph replay")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run sa_copy_u32 over 256 MiB three times (counter calibration)")
     ap.add_argument("--pool", type=int, default=64, help="serving: distinct jobs generated")
     ap.add_argument("--jobs", type=int, default=300, help="serving: jobs per arrival-rate run")
     ap.add_argument("--workers", type=int, default=3, help="serving: server worker streams")
@@ -297,6 +299,13 @@ def main():
         ovl = pkg.sa_overlaps(text, sa, isa, lcp, r.min_len)
         return sa, isa, lcp, ovl
 
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            pkg.sa_copy_u32(dst, src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 256 MiB read + 256 MiB written")
     for i in range(args.warmup):
         out = step()
         torch.cuda.synchronize()
@@ -332,9 +341,15 @@ def main():
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     traffic = None
     if os.path.exists(args.traffic):
+        # counter-derived HBM bytes per launch, valid only for the kernel source they were taken on
+        import hashlib
+        csrc = os.path.join(ROOT, "paper_1404_3456_amd", "csrc")
+        h = hashlib.sha256(open(os.path.join(csrc, "radix.hip"), "rb").read() +
+                           open(os.path.join(csrc, "device.hpp"), "rb").read()).hexdigest()
         try:
             tr = json.load(open(args.traffic))
-            traffic = tr.get("bytes_per_launch")
+            if tr.get("source_sha256") == h and (tuning is None):
+                traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
