@@ -483,7 +483,7 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
 // active count and h are read from device memory (state[kStActive], state[kStH]); the number
 // of keys written goes to state[kStKeys].
 constexpr int kKbBlock = 256;
-constexpr int kKbItems = 8;
+constexpr int kKbItems = 16;
 constexpr int kKbTile = kKbBlock * kKbItems;
 
 template <int D>
@@ -516,17 +516,19 @@ __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restric
         if (tile >= ntiles) break;
         const uint32_t tbase = tile * kKbTile;
         uint32_t r[kKbItems];
-        uint64_t act[kKbItems];
 #pragma unroll
         for (int j = 0; j < kKbItems; ++j) {
             const uint32_t p = tbase + j * kKbBlock + tid;  // striped: a wave covers 64 in a row
             r[j] = p < n ? rank[p] : kDone;
-            act[j] = ballot((r[j] & kDone) == 0);
-            if (lane == 0) s_chunk[j * W + wave] = uint32_t(popc64(act[j]));
+        }
+#pragma unroll
+        for (int j = 0; j < kKbItems; ++j) {
+            const uint64_t act = ballot((r[j] & kDone) == 0);
+            if (lane == 0) s_chunk[j * W + wave] = uint32_t(popc64(act));
         }
         __syncthreads();
         if (wave == 0) {
-            // chunks are ordered (j, wave); <= 64 of them: one lane each
+            // chunks are ordered (j, wave); kKbItems * W <= 64 of them: one lane each
             uint32_t c = lane < uint32_t(kKbItems * W) ? s_chunk[lane] : 0u;
             uint32_t inc = wave_incl_scan<Sum32>(c);
             uint32_t tile_total = __shfl(inc, kKbItems * W - 1);
@@ -539,13 +541,14 @@ __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restric
 #pragma unroll
         for (int j = 0; j < kKbItems; ++j) {
             const uint32_t p = tbase + j * kKbBlock + tid;
+            const uint64_t act = ballot((r[j] & kDone) == 0);
             if ((r[j] & kDone) == 0) {
                 uint32_t r2 = 0;
                 if (p + h < n) r2 = rank[p + h] & kRankMask;
                 else raise_err(err, kErrRange);
                 const uint64_t k = ((uint64_t(r[j]) & rmask) << rbits) | (uint64_t(r2) & rmask);
                 const uint32_t o = uint32_t(s_excl) + s_chunk[j * W + wave] +
-                                   uint32_t(popc64(act[j] & lanemask_lt()));
+                                   uint32_t(popc64(act & lanemask_lt()));
                 if (o < active) {
                     keys[o] = k;
                     vals[o] = p;

@@ -41,95 +41,108 @@ constexpr int kRuTile = kRuBlock * kRuItems;
 //   label(i)  = S[g] where g is the last head at or before i.
 // Writes sa[S[i]] = V[i], rank[V[i]] = label | (single ? kDone : 0), and the slots of items
 // that are not singletons, compacted in order, to S_new; their count to state[kStNext].
+// In a doubling round the key's upper half is the item's previous label, so rank[V[i]] is
+// only rewritten when the label changes or the item becomes a singleton.
+// One tile per workgroup (tiles by ticket); the grid covers an upper bound on A and surplus
+// workgroups return at once.
 __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     const uint64_t *__restrict__ K, const uint32_t *__restrict__ V, const uint32_t *__restrict__ S,
-    uint32_t n, int round0, uint32_t h0, int32_t *__restrict__ sa, uint32_t *__restrict__ rank,
-    uint32_t *__restrict__ S_new, uint64_t *lbflags, uint32_t *tick, uint32_t *state,
-    uint32_t *err) {
+    uint32_t n, int round0, uint32_t h0, int rbits, int32_t *__restrict__ sa,
+    uint32_t *__restrict__ rank, uint32_t *__restrict__ S_new, uint64_t *lbflags, uint32_t *tick,
+    uint32_t *state, uint32_t *err) {
     __shared__ uint64_t s_k[kRuTile + 2];
+    __shared__ uint32_t s_s[kRuTile];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_w[kRuBlock / kWave];
     __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t A = state[kStActive];
     const uint32_t ntiles = (A + kRuTile - 1) / kRuTile;
-    while (true) {
-        __syncthreads();
-        if (tid == 0) s_tile = ticket(tick);
-        __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= ntiles) break;
-        const uint32_t tbase = tile * kRuTile;
-        // keys of the tile plus one neighbour on each side (s_k[1 + i] = K[tbase + i])
-        for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock)
-            s_k[1 + i] = (tbase + i < A) ? K[tbase + i] : 0;
-        if (tid == 0) s_k[0] = tbase > 0 ? K[tbase - 1] : 0;
-        if (tid == 1) s_k[kRuTile + 1] = (tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
-        __syncthreads();
+    if (tid == 0) s_tile = ticket(tick);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+    const uint32_t tbase = tile * kRuTile;
+    // keys and slots of the tile (coalesced), one key of neighbour on each side
+    for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock) {
+        const bool in = tbase + i < A;
+        s_k[1 + i] = in ? K[tbase + i] : 0;
+        s_s[i] = in ? (S ? S[tbase + i] : tbase + i) : 0;
+    }
+    if (tid == 0) s_k[0] = tbase > 0 ? K[tbase - 1] : 0;
+    if (tid == 1) s_k[kRuTile + 1] = (tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
+    const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
+    uint32_t v[kRuItems];
+#pragma unroll
+    for (int j = 0; j < kRuItems; ++j) {
+        const uint32_t i = tbase + first + j;
+        v[j] = i < A ? V[i] : 0;  // issued before the scan and look-back
+    }
+    __syncthreads();
 
-        const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
-        bool head[kRuItems + 1];
+    bool head[kRuItems + 1];
 #pragma unroll
-        for (int j = 0; j <= kRuItems; ++j) {
-            const uint32_t li = first + j;
-            const uint32_t i = tbase + li;
-            bool h = true;
-            if (i < A && i > 0) {
-                const uint64_t k = s_k[1 + li];
-                h = (k != s_k[li]) || (round0 && (k & 31u) < uint64_t(h0));
+    for (int j = 0; j <= kRuItems; ++j) {
+        const uint32_t li = first + j;
+        const uint32_t i = tbase + li;
+        bool h = true;
+        if (i < A && i > 0) {
+            const uint64_t k = s_k[1 + li];
+            h = (k != s_k[li]) || (round0 && (k & 31u) < uint64_t(h0));
+        }
+        head[j] = h;  // i >= A: counts as a head for the single() test of i-1
+    }
+    uint32_t cnt = 0, last = 0;
+#pragma unroll
+    for (int j = 0; j < kRuItems; ++j) {
+        const uint32_t i = tbase + first + j;
+        if (i < A) {
+            if (head[j]) last = i + 1;
+            if (!(head[j] && head[j + 1])) ++cnt;
+        }
+    }
+    // exclusive (count, last-head) scan over the workgroup, then over tiles
+    const uint64_t mine = (uint64_t(cnt) << 31) | last;
+    uint64_t inc = wave_incl_scan<CountLastOp>(mine);
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint64_t before = 0, tile_agg = 0;
+#pragma unroll
+    for (int w = 0; w < kRuBlock / kWave; ++w) {
+        if (uint32_t(w) < wave) before = CountLastOp::combine(before, s_w[w]);
+        tile_agg = CountLastOp::combine(tile_agg, s_w[w]);
+    }
+    uint64_t lane_excl = __shfl_up(inc, 1);
+    if (lane == 0) lane_excl = 0;
+    if (wave == 0) {
+        uint64_t ex = lookback_tile<CountLastOp>(lbflags, int(tile), tile_agg, err);
+        if (lane == 0) s_excl = ex;
+        if (lane == 0 && tile == ntiles - 1)
+            state[kStNext] = uint32_t(CountLastOp::combine(ex, tile_agg) >> 31);
+    }
+    __syncthreads();
+    const uint64_t state_in = CountLastOp::combine(CountLastOp::combine(s_excl, before), lane_excl);
+    uint32_t out = uint32_t(state_in >> 31);
+    uint32_t g1 = uint32_t(state_in & CountLastOp::kLastMask);  // last head index + 1
+    const uint64_t lmask = (uint64_t(1) << rbits) - 1;
+#pragma unroll
+    for (int j = 0; j < kRuItems; ++j) {
+        const uint32_t li = first + j;
+        const uint32_t i = tbase + li;
+        if (i < A) {
+            if (head[j]) g1 = i + 1;
+            const bool single = head[j] && head[j + 1];
+            const uint32_t g = g1 - 1;  // i == 0 is always a head, so g1 >= 1
+            const uint32_t slot = s_s[li];
+            const uint32_t label = g >= tbase ? s_s[g - tbase] : (S ? S[g] : g);
+            if (slot >= n || v[j] >= n || label >= n) {  // inconsistent input: report only
+                raise_err(err, kErrRange);
+                continue;
             }
-            head[j] = h;  // i >= A: counts as a head for the single() test of i-1
-        }
-        uint32_t cnt = 0, last = 0;
-#pragma unroll
-        for (int j = 0; j < kRuItems; ++j) {
-            const uint32_t i = tbase + first + j;
-            if (i < A) {
-                if (head[j]) last = i + 1;
-                if (!(head[j] && head[j + 1])) ++cnt;
-            }
-        }
-        // exclusive (count, last-head) scan over the workgroup, then over tiles
-        const uint64_t mine = (uint64_t(cnt) << 31) | last;
-        uint64_t inc = wave_incl_scan<CountLastOp>(mine);
-        if (lane == kWave - 1) s_w[wave] = inc;
-        __syncthreads();
-        uint64_t before = 0, tile_agg = 0;
-#pragma unroll
-        for (int w = 0; w < kRuBlock / kWave; ++w) {
-            if (uint32_t(w) < wave) before = CountLastOp::combine(before, s_w[w]);
-            tile_agg = CountLastOp::combine(tile_agg, s_w[w]);
-        }
-        uint64_t lane_excl = __shfl_up(inc, 1);
-        if (lane == 0) lane_excl = 0;
-        if (wave == 0) {
-            uint64_t ex = lookback_tile<CountLastOp>(lbflags, int(tile), tile_agg, err);
-            if (lane == 0) s_excl = ex;
-            if (lane == 0 && tile == ntiles - 1)
-                state[kStNext] = uint32_t(CountLastOp::combine(ex, tile_agg) >> 31);
-        }
-        __syncthreads();
-        const uint64_t state_in = CountLastOp::combine(CountLastOp::combine(s_excl, before), lane_excl);
-        uint32_t out = uint32_t(state_in >> 31);
-        uint32_t g1 = uint32_t(state_in & CountLastOp::kLastMask);  // last head index + 1
-#pragma unroll
-        for (int j = 0; j < kRuItems; ++j) {
-            const uint32_t i = tbase + first + j;
-            if (i < A) {
-                if (head[j]) g1 = i + 1;
-                const bool single = head[j] && head[j + 1];
-                const uint32_t g = g1 - 1;  // i == 0 is always a head, so g1 >= 1
-                const uint32_t slot = S ? S[i] : i;
-                const uint32_t label = S ? S[g] : g;
-                const uint32_t v = V[i];
-                if (slot >= n || v >= n || label >= n) {  // inconsistent input: report only
-                    raise_err(err, kErrRange);
-                    continue;
-                }
-                sa[slot] = int32_t(v);
-                rank[v] = label | (single ? kDone : 0u);
-                if (!single) S_new[out++] = slot;
-            }
+            sa[slot] = int32_t(v[j]);
+            const bool same = !round0 && uint32_t((s_k[1 + li] >> rbits) & lmask) == label;
+            if (single || !same) rank[v[j]] = label | (single ? kDone : 0u);
+            if (!single) S_new[out++] = slot;
         }
     }
 }
@@ -191,28 +204,19 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
 }
 
 static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32_t *S,
-                              int64_t a_bound, int64_t n, bool round0, int h0, int32_t *sa,
-                              uint32_t *rank, uint32_t *S_new, uint64_t *lbflags, uint32_t *tick,
-                              uint32_t *state, hipStream_t s) {
-    const int64_t tiles = (a_bound + kRuTile - 1) / kRuTile;
-    static int per_cu = 0;
-    if (!per_cu) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rank_update, kRuBlock, 0) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-    }
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int64_t grid = int64_t(cus) * per_cu;
-    if (grid > tiles) grid = tiles;
-    if (grid < 1) grid = 1;
-    SA_TRY(launch_fill_u64(lbflags, tiles > 0 ? tiles : 1, 0, s));
+                              int64_t a_bound, int64_t n, bool round0, int h0, int rbits,
+                              int32_t *sa, uint32_t *rank, uint32_t *S_new, uint64_t *lbflags,
+                              uint32_t *tick, uint32_t *state, hipStream_t s) {
+    int64_t tiles = (a_bound + kRuTile - 1) / kRuTile;
+    if (tiles < 1) tiles = 1;
+    SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     // algorithmic bytes: read K (8) + V (4) + S (4 when present); write sa (4) + rank (4) +
     // S_new (4, upper bound)
     TimedScope ts("rank_update", double(a_bound) * (S ? 28.0 : 24.0), s);
-    hipLaunchKernelGGL(k_rank_update, dim3(unsigned(grid)), dim3(kRuBlock), 0, s, K, V, S,
-                       uint32_t(n), int(round0), uint32_t(h0), sa, rank, S_new, lbflags, tick,
-                       state, state + kStErr);
+    hipLaunchKernelGGL(k_rank_update, dim3(unsigned(tiles)), dim3(kRuBlock), 0, s, K, V, S,
+                       uint32_t(n), int(round0), uint32_t(h0), rbits, sa, rank, S_new, lbflags,
+                       tick, state, state + kStErr);
     ts.finish();
     SA_HIP(hipGetLastError());
     return SA_OK;
@@ -264,8 +268,8 @@ struct Build {
         SA_TRY(launch_key0(L.packed, L.sepmask, n, h0, set_off_dev, n_sets, key0_bits, L.sb, 0, t, s, &nparts));
         int cur = 0;
         SA_TRY(sort_run(L.sb, 0, nullptr, n, 0, key0_bits, t, nparts, s, &cur));
-        SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], nullptr, n, n, true, h0, sa, rank,
-                                  L.slots[0], L.lbflags, L.tickets, L.state, s));
+        SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], nullptr, n, n, true, h0, rbits,
+                                  sa, rank, L.slots[0], L.lbflags, L.tickets, L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
@@ -281,7 +285,7 @@ struct Build {
         int cur = 0;
         SA_TRY(sort_run(L.sb, 0, L.state + kStActive, a_bound, 0, bits, t, nparts, s, &cur));
         SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], L.slots[sl], a_bound, n, false, h0,
-                                  sa, rank, L.slots[sl ^ 1], L.lbflags, L.tickets, L.state, s));
+                                  rbits, sa, rank, L.slots[sl ^ 1], L.lbflags, L.tickets, L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
