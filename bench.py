@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--max-total", type=int, default=0,
                     help="batched workload: stop adding sets once this many characters are drawn")
     ap.add_argument("--no-graph", action="store_true", help="batched workload: no hipGraph replay")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose digit width, tile shape (and, batched, set packing) by measurement first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run sa_copy_u32 over 256 MiB three times (counter calibration)")
     ap.add_argument("--pool", type=int, default=64, help="serving: distinct jobs generated")
@@ -91,6 +93,13 @@ def bench_batched(args, pkg, torch, np):
     tuning = None
     if args.digit_bits or args.block or args.items:
         tuning = pkg.Tuning(args.digit_bits, args.block, args.items, 0)
+    tune_report = None
+    if args.autotune:
+        from paper_1404_3456_amd import autotune
+        tuning, tune_report = autotune.autotune(
+            text, off, candidates=[(8, 512, 16), (9, 512, 16), (9, 256, 16), (11, 512, 16)],
+            seg_packs=(0, 1 << 28), reps=1, use_cache=False, log=log)
+        log(f"autotuned: {tuning}")
 
     def batched():
         sa, isa = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=not args.no_graph)
@@ -144,6 +153,7 @@ def bench_batched(args, pkg, torch, np):
         "batched_Msuffixes_per_s": round(cat.size / tb / 1e6, 1),
         "overlap_rows": int(ovl_b.shape[0]),
         "rows_match_plain": bool(same),
+        "autotune": tune_report,
     }
     print(json.dumps(out), flush=True)
 
@@ -185,7 +195,7 @@ def bench_serving(args, pkg, torch, np):
                             break
                         time.sleep(min(0.0005, target - now))
                     lag = time.perf_counter() - target
-                    jid = srv.asm_submit(texts[order[i]], 40)
+                    jid = srv.asm_submit(texts[order[i]], 40, borrow=True)
                     with lock:
                         pending[jid] = (i, lag)
                 done.set()
@@ -290,6 +300,10 @@ def main():
     log(f"workload {r.name}: n={r.n} m={r.m} sha256={r.sha256()[:16]}")
     dev = torch.device("cuda:0")
     text = torch.from_numpy(r.text).to(dev)
+    if args.autotune:
+        from paper_1404_3456_amd import autotune
+        tuning, rep = autotune.autotune(text, reps=2, use_cache=False, log=log)
+        log(f"autotuned: {tuning} ({rep['ms']} ms)")
     n = r.n
     stream = torch.cuda.current_stream()
 

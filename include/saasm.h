@@ -50,10 +50,12 @@ enum {
 };
 
 /* Launch tuning of the radix sort; a zero field means "use the default".
- *   digit_bits       4, 8 or 11 bits per LSD pass
+ *   digit_bits       4, 8, 9 or 11 bits per LSD pass
  *   block_threads    256 or 512 threads per workgroup (4 or 8 wave64 wavefronts; default 512)
  *   items_per_thread 8 or 16 keys per thread (tile = block_threads * items_per_thread)
- *   seg_pack         reserved for the batched path; must be 0 here                          */
+ *   seg_pack         sa_build_batched only: at most this many characters per build
+ *                    (consecutive texts are packed greedily; 0 = all texts in one build);
+ *                    must be 0 for the other entry points                                 */
 typedef struct {
     int32_t digit_bits;
     int32_t block_threads;
@@ -134,10 +136,13 @@ int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
  *               of text s, in concatenated coordinates (subtract set_off_h[s] for local ones)
  *   isa_or_null [n] optional out: inverse of sa
  *   use_graph   nonzero: the doubling rounds are recorded once as a hipGraph and replayed
+ * The workspace size depends on the packing when tune->seg_pack > 0: pass the same offsets to
+ * sa_build_batched_ws_bytes (NULL offsets give the size for one build of all texts).
  * sa_lcp and sa_overlaps accept the concatenated text with this sa/isa unchanged: LCP is 0 at
  * every block start and no overlap pairs reads of different texts.  Synchronises the stream
  * once per round (once per graph replay). */
-int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const sa_tuning *tune_or_null);
+int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const int64_t *set_off_h_or_null,
+                                  const sa_tuning *tune_or_null);
 int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h, int32_t n_sets,
                      int32_t *sa, int32_t *isa_or_null, void *ws, int64_t ws_bytes,
                      const sa_tuning *tune_or_null, int32_t use_graph, int32_t *rounds_h,
@@ -156,8 +161,9 @@ int64_t sa_lcp_ws_bytes(int64_t n);
 int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
            int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream);
 
-/* Positions scanned per thread by sa_lcp (each thread restarts Kasai's carried bound at its
- * first position; any value gives the same result).  Process-wide; default 4. */
+/* Positions scanned per thread by sa_lcp: 1, 2, 4, 8 or 16 (each thread restarts Kasai's
+ * carried bound at its first position; any value gives the same result).  Process-wide;
+ * default 4. */
 int sa_lcp_set_chunk(int32_t chunk);
 
 /* ---------------------------------------------------------------------------------------- */
@@ -213,11 +219,17 @@ typedef struct {
 int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_jobs_per_batch,
                       int32_t workers, int32_t mode, asm_server **out);
 
-/* asm_submit: queue one job.  The text (host memory, same conventions as sa_build) is copied,
- * so the caller may reuse it at once.  Returns SA_ERR_ALPHABET / SA_ERR_INVALID for a bad text
- * and SA_ERR_NOMEM when the job alone exceeds the budget; the server keeps running. */
+/* asm_submit: queue one job (host text, same conventions as sa_build).
+ *   flags 0           the text is validated and copied, so the caller may reuse it at once;
+ *                     a bad text returns SA_ERR_ALPHABET / SA_ERR_INVALID here
+ *   flags ASM_BORROW  no copy: the caller keeps the text valid and unchanged until asm_poll
+ *                     reports a final status; the alphabet is checked by the worker that runs
+ *                     the job, and a bad text makes that job (only) finish with SA_ERR_ALPHABET
+ * Returns SA_ERR_NOMEM when the job alone exceeds the budget.  The server keeps running after
+ * any rejected job. */
+enum { ASM_BORROW = 1 };
 int asm_submit(asm_server *server, const uint8_t *text_h, int64_t n, int32_t min_len,
-               uint64_t *job_id_h);
+               int32_t flags, uint64_t *job_id_h);
 
 /* asm_poll: status and, once done, results of a job.  Returns SA_PENDING while it runs, SA_OK
  * once res_h->status is final (which may itself be an error), SA_ERR_NOTFOUND for an unknown

@@ -17,6 +17,7 @@ SA_ERR_NOMEM = -4
 SA_ERR_CAPACITY = -5
 SA_ERR_HIP = -6
 SA_ERR_NOTFOUND = -7
+ASM_BORROW = 1
 
 _lib = None
 
@@ -75,7 +76,7 @@ def load():
         "sa_sort_pairs": ([P, P, I64, I32, I32, P, I64, TP, P], ctypes.c_int),
         "sa_build_ws_bytes": ([I64, TP], I64),
         "sa_build": ([P, I64, P, P, P, I64, TP, P, P], ctypes.c_int),
-        "sa_build_batched_ws_bytes": ([I64, I32, TP], I64),
+        "sa_build_batched_ws_bytes": ([I64, I32, P, TP], I64),
         "sa_build_batched": ([P, I64, P, I32, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
         "sa_lcp_ws_bytes": ([I64], I64),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
@@ -87,7 +88,7 @@ def load():
         "sa_timing_get": ([ctypes.c_char_p, P, P, P], ctypes.c_int),
         "sa_copy_u32": ([P, P, I64, P], ctypes.c_int),
         "asm_server_create": ([P, I64, I32, I32, I32, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
-        "asm_submit": ([P, P, I64, I32, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "asm_submit": ([P, P, I64, I32, I32, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "asm_poll": ([P, ctypes.c_uint64, ctypes.POINTER(_AsmResult)], ctypes.c_int),
         "asm_release": ([P, ctypes.c_uint64], ctypes.c_int),
         "asm_server_stats": ([P, P], ctypes.c_int),
@@ -229,8 +230,11 @@ def sa_build(text, isa: bool = True, tuning=None, stream=None, return_rounds: bo
     return sa, isa_t
 
 
-def sa_build_batched_ws_bytes(n: int, n_sets: int, tuning=None) -> int:
-    return int(load().sa_build_batched_ws_bytes(n, n_sets, _tune(tuning)))
+def sa_build_batched_ws_bytes(n: int, n_sets: int, tuning=None, set_off=None) -> int:
+    import numpy as np
+    off = None if set_off is None else np.ascontiguousarray(set_off, dtype=np.int64)
+    ptr = None if off is None else off.ctypes.data_as(ctypes.c_void_p)
+    return int(load().sa_build_batched_ws_bytes(n, n_sets, ptr, _tune(tuning)))
 
 
 def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bool = True,
@@ -247,7 +251,7 @@ def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bo
     n_sets = off.size - 1
     sa = torch.empty(n, dtype=torch.int32, device=t.device)
     isa_t = torch.empty(n, dtype=torch.int32, device=t.device) if isa else None
-    wsb = sa_build_batched_ws_bytes(n, n_sets, tuning)
+    wsb = sa_build_batched_ws_bytes(n, n_sets, tuning, off)
     if wsb < 0:
         raise SaasmError(SA_ERR_INVALID, "bad size, set count or tuning")
     ws = _ws(wsb, t.device)
@@ -350,13 +354,18 @@ class AsmServer:
                                      int(workers), int(mode), ctypes.byref(h)))
         self._h = h
         self._lib = lib
+        self._borrowed = {}
 
-    def asm_submit(self, text, min_len: int) -> int:
+    def asm_submit(self, text, min_len: int, borrow: bool = False) -> int:
+        """Queue a job.  With borrow=True the server reads `text` in place (no copy); the
+        binding keeps a reference to it until the job is released."""
         import numpy as np
         t = np.ascontiguousarray(text, dtype=np.uint8)
         jid = ctypes.c_uint64(0)
         _check(self._lib.asm_submit(self._h, t.ctypes.data_as(ctypes.c_void_p), t.size,
-                                    int(min_len), ctypes.byref(jid)))
+                                    int(min_len), ASM_BORROW if borrow else 0, ctypes.byref(jid)))
+        if borrow:
+            self._borrowed[int(jid.value)] = t
         return int(jid.value)
 
     def asm_poll(self, job_id: int):
@@ -385,6 +394,7 @@ class AsmServer:
 
     def asm_release(self, job_id: int):
         _check(self._lib.asm_release(self._h, ctypes.c_uint64(job_id)))
+        self._borrowed.pop(int(job_id), None)
 
     def asm_server_stats(self):
         import numpy as np

@@ -1,4 +1,5 @@
 // api.hip -- error reporting, version, tuning resolution and per-kernel event timing.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -25,8 +26,8 @@ int resolve_tuning(const sa_tuning *tu, Tune *out) {
         if (tu->items_per_thread) t.items = tu->items_per_thread;
         if (tu->seg_pack != 0) return fail(SA_ERR_INVALID, "seg_pack must be 0 for this call");
     }
-    if (t.dbits != 4 && t.dbits != 8 && t.dbits != 11)
-        return fail(SA_ERR_INVALID, "digit_bits must be 4, 8 or 11");
+    if (t.dbits != 4 && t.dbits != 8 && t.dbits != 9 && t.dbits != 11)
+        return fail(SA_ERR_INVALID, "digit_bits must be 4, 8, 9 or 11");
     if (t.block != 256 && t.block != 512) return fail(SA_ERR_INVALID, "block_threads must be 256 or 512");
     if (t.items != 8 && t.items != 16) return fail(SA_ERR_INVALID, "items_per_thread must be 8 or 16");
     *out = t;
@@ -44,7 +45,11 @@ struct Pending {
     hipEvent_t a, b;
     std::string key;
     double bytes;
+    double per_item;
+    int64_t tag;  // -1: bytes final; else waiting for timing_round_items
 };
+std::atomic<int64_t> g_next_tag{1};
+thread_local int64_t t_tag = -1;
 std::mutex g_mu;
 bool g_on = false;
 std::vector<Pending> g_pending;
@@ -79,6 +84,12 @@ TimedScope::TimedScope(const char *k, double b, hipStream_t s) : key(k), bytes(b
     }
 }
 
+TimedScope::TimedScope(const char *k, double fixed_bytes, double per_item_bytes, hipStream_t s)
+    : TimedScope(k, fixed_bytes, s) {
+    per_item = per_item_bytes;
+    tag = t_tag;
+}
+
 void TimedScope::finish() {
     if (!start) return;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -89,15 +100,46 @@ void TimedScope::finish() {
         start = nullptr;
         return;
     }
-    g_pending.push_back(Pending{start, end, key, bytes});
+    g_pending.push_back(Pending{start, end, key, bytes, per_item, tag});
     start = nullptr;
 }
 
-void timing_flush() {
+int64_t timing_round_begin() {
+    t_tag = g_next_tag++;
+    return t_tag;
+}
+
+void timing_round_items(int64_t tag, int64_t items) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &p : g_pending) {
+        if (p.tag != tag) continue;
+        if (items <= 0) {
+            p.bytes = -1.0;  // empty round: dropped when resolved
+        } else {
+            p.bytes += p.per_item * double(items);
+        }
+        p.tag = -1;
+    }
+}
+
+// Resolves pending launch timings; when `block` is false only those whose end event has
+// already completed (so it never waits on device work).
+static void timing_resolve(bool block) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    size_t keep = 0;
+    for (size_t i = 0; i < g_pending.size(); ++i) {
+        Pending &p = g_pending[i];
+        if (p.tag >= 0 && !block) {  // item count not known yet
+            g_pending[keep++] = p;
+            continue;
+        }
+        if (!block && hipEventQuery(p.b) != hipSuccess) {
+            g_pending[keep++] = p;
+            continue;
+        }
         float ms = 0.f;
-        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        if (p.tag < 0 && p.bytes >= 0.0 && hipEventSynchronize(p.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             Acc &a = g_acc[p.key];
             a.launches += 1;
             a.ms += ms;
@@ -106,8 +148,11 @@ void timing_flush() {
         g_pool.push_back(p.a);
         g_pool.push_back(p.b);
     }
-    g_pending.clear();
+    g_pending.resize(keep);
 }
+
+void timing_flush() { timing_resolve(true); }
+void timing_poll() { timing_resolve(false); }
 
 }  // namespace saasm
 

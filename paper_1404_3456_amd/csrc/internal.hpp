@@ -61,15 +61,23 @@ int resolve_tuning(const sa_tuning *t, Tune *out);
 bool timing_on();
 struct TimedScope {
     // Records a start event on `stream` when timing is on; finish() records the end event and
-    // files the launch under `key` with `bytes` algorithmic bytes.
+    // files the launch under `key` with `bytes` algorithmic bytes.  The second form is for
+    // launches whose item count is only known on the device: the record waits until
+    // timing_round_items() gives the count for the calling thread's current round tag.
     const char *key;
     double bytes;
+    double per_item = 0.0;
+    int64_t tag = -1;
     hipStream_t stream;
     hipEvent_t start = nullptr;
     TimedScope(const char *k, double b, hipStream_t s);
+    TimedScope(const char *k, double fixed_bytes, double per_item_bytes, hipStream_t s);
     void finish();
 };
-void timing_flush();  // resolve pending events (call after a stream synchronisation)
+int64_t timing_round_begin();                       // new tag for the calling thread's round
+void timing_round_items(int64_t tag, int64_t items);  // item count of that round (0: drop)
+void timing_flush();  // resolve pending events (waits for them)
+void timing_poll();   // resolve only the pending events that have already completed
 void timing_pause(bool on);  // calling thread: no events while a stream is being captured
 
 // ---- kernels exposed across translation units ----------------------------------------------

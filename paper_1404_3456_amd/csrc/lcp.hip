@@ -29,26 +29,39 @@ __device__ __forceinline__ uint32_t sepwin32(const uint32_t *__restrict__ sepmas
     return uint32_t((x << o) >> 32);
 }
 
+template <int CH>
 __global__ __launch_bounds__(256) void k_kasai(const uint32_t *__restrict__ packed,
                                                const uint32_t *__restrict__ sepmask,
                                                const int32_t *__restrict__ sa,
                                                const int32_t *__restrict__ isa,
                                                int32_t *__restrict__ lcp, uint32_t n,
-                                               uint32_t chunk, uint32_t *err) {
+                                               uint32_t *err) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t p0 = uint64_t(c) * chunk;
+    const uint64_t p0 = uint64_t(c) * CH;
     if (p0 >= n) return;
-    const uint32_t p1 = uint32_t((p0 + chunk < n) ? p0 + chunk : n);
+    // all index loads of the chunk first (they do not depend on the carried length)
+    int32_t iv[CH];
+    uint32_t qv[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) iv[k] = (p0 + k < n) ? isa[p0 + k] : -1;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int32_t i = iv[k];
+        qv[k] = (i > 0 && uint32_t(i) < n) ? uint32_t(sa[i - 1]) : 0xffffffffu;
+    }
     uint32_t h = 0;
-    for (uint32_t p = uint32_t(p0); p < p1; ++p) {
-        const int32_t i = isa[p];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const uint32_t p = uint32_t(p0) + k;
+        if (p >= n) break;
+        const int32_t i = iv[k];
         if (i <= 0 || uint32_t(i) >= n) {
             if (i == 0) lcp[0] = 0;
             else raise_err(err, kErrRange);
             h = 0;
             continue;
         }
-        const uint32_t q = uint32_t(sa[i - 1]);
+        const uint32_t q = qv[k];
         if (q >= n) {
             raise_err(err, kErrRange);
             h = 0;
@@ -63,9 +76,9 @@ __global__ __launch_bounds__(256) void k_kasai(const uint32_t *__restrict__ pack
             const uint32_t sp = sepwin32(sepmask, p + h) | sepwin32(sepmask, q + h);
             const uint32_t md = d ? uint32_t(__clzll((long long)d)) >> 1 : 32u;
             const uint32_t ms = sp ? uint32_t(__clz(sp)) : 32u;
-            const uint32_t k = md < ms ? md : ms;
-            h += k;
-            if (k < 32) break;
+            const uint32_t kk = md < ms ? md : ms;
+            h += kk;
+            if (kk < 32) break;
         }
         lcp[i] = int32_t(h);
         if (h > 0) --h;
@@ -103,10 +116,16 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
     SA_TRY(launch_pack(text, n, packed, sepmask, wordcnt, err, stream));
     const uint32_t chunk = g_lcp_chunk;
     const int64_t threads = (n + chunk - 1) / chunk;
+    const dim3 grid(unsigned((threads + 255) / 256)), block(256);
     // algorithmic bytes: isa[p] (4) + sa[isa[p]-1] (4) + lcp write (4) per position
     TimedScope ts("kasai", double(n) * 12.0, stream);
-    hipLaunchKernelGGL(k_kasai, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, stream,
-                       packed, sepmask, sa, isa, lcp, uint32_t(n), chunk, err);
+    switch (chunk) {
+        case 1: hipLaunchKernelGGL(k_kasai<1>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
+        case 2: hipLaunchKernelGGL(k_kasai<2>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
+        case 4: hipLaunchKernelGGL(k_kasai<4>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
+        case 8: hipLaunchKernelGGL(k_kasai<8>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
+        default: hipLaunchKernelGGL(k_kasai<16>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
+    }
     ts.finish();
     SA_HIP(hipGetLastError());
     return SA_OK;
@@ -114,7 +133,8 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
 
 // Chunk length of the Kasai scan (positions per thread); exposed for tuning sweeps.
 extern "C" int sa_lcp_set_chunk(int32_t chunk) {
-    if (chunk < 1 || chunk > 4096) return fail(SA_ERR_INVALID, "sa_lcp_set_chunk: 1..4096");
+    if (chunk != 1 && chunk != 2 && chunk != 4 && chunk != 8 && chunk != 16)
+        return fail(SA_ERR_INVALID, "sa_lcp_set_chunk: 1, 2, 4, 8 or 16");
     g_lcp_chunk = uint32_t(chunk);
     return SA_OK;
 }

@@ -95,34 +95,51 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t *__restrict__ keys,
 }
 
 // Sum the partial histograms of one pass and scan them into exclusive digit bases (one
-// workgroup per pass).
+// 1024-thread workgroup per pass; every digit's partials are split over several threads).
+constexpr int kHsBlock = 1024;
 template <int D>
-__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ part, int nparts,
-                                                   int passes, uint32_t *__restrict__ gbase) {
+__global__ __launch_bounds__(kHsBlock) void k_hist_scan(const uint32_t *__restrict__ part,
+                                                        int nparts, int passes,
+                                                        uint32_t *__restrict__ gbase) {
     constexpr int R = 1 << D;
-    constexpr int PER = (R + 255) / 256;
-    __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_sum[R];
-    for (int d = threadIdx.x; d < R; d += 256) {
-        uint32_t acc = 0;
-        const uint32_t *src = part + size_t(blockIdx.x) * R + d;
-        for (int w = 0; w < nparts; ++w) acc += src[size_t(w) * passes * R];
-        s_sum[d] = acc;
+    constexpr int T = R >= kHsBlock ? 1 : kHsBlock / R;  // threads per digit
+    constexpr int PER = (R + kHsBlock - 1) / kHsBlock;    // digits per thread in the scan
+    __shared__ uint32_t s_w[kHsBlock / kWave];
+    __shared__ uint32_t s_part[R * T];
+    const uint32_t *src = part + size_t(blockIdx.x) * R;
+    const size_t stride = size_t(passes) * R;
+    for (int idx = threadIdx.x; idx < R * T; idx += kHsBlock) {
+        const int d = idx % R, k = idx / R;
+        uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int w = k;
+        for (; w + 3 * T < nparts; w += 4 * T) {
+            a0 += src[size_t(w) * stride + d];
+            a1 += src[size_t(w + T) * stride + d];
+            a2 += src[size_t(w + 2 * T) * stride + d];
+            a3 += src[size_t(w + 3 * T) * stride + d];
+        }
+        for (; w < nparts; w += T) a0 += src[size_t(w) * stride + d];
+        s_part[idx] = a0 + a1 + a2 + a3;
     }
     __syncthreads();
     uint32_t *g = gbase + blockIdx.x * R;
     uint32_t v[PER], sum = 0;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        int d = threadIdx.x * PER + j;
-        v[j] = d < R ? s_sum[d] : 0;
-        sum += v[j];
+        const int d = threadIdx.x * PER + j;
+        uint32_t c = 0;
+        if (d < R) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) c += s_part[k * R + d];
+        }
+        v[j] = c;
+        sum += c;
     }
     uint32_t total;
-    uint32_t run = block_excl_sum<256>(sum, s_w, &total);
+    uint32_t run = block_excl_sum<kHsBlock>(sum, s_w, &total);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        int d = threadIdx.x * PER + j;
+        const int d = threadIdx.x * PER + j;
         if (d < R) g[d] = run;
         run += v[j];
     }
@@ -144,6 +161,7 @@ int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, con
     switch (t.dbits) {
         case 4: hipLaunchKernelGGL(k_hist<4>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
         case 8: hipLaunchKernelGGL(k_hist<8>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
+        case 9: hipLaunchKernelGGL(k_hist<9>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
         case 11: hipLaunchKernelGGL(k_hist<11>, dim3(hist_grid(n)), dim3(256), lds, s, b.keys[cur], uint32_t(n), bit_lo, bits, P, b.hist); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
@@ -366,9 +384,10 @@ int sort_run(const SortBufs &b, int cur, const uint32_t *count_dev, int64_t n, i
     if (P == 0 || n <= 1) return SA_OK;
     const int R = t.radix();
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_hist_scan<4>, dim3(P), dim3(256), 0, s, b.hist, nparts, P, b.gbase); break;
-        case 8: hipLaunchKernelGGL(k_hist_scan<8>, dim3(P), dim3(256), 0, s, b.hist, nparts, P, b.gbase); break;
-        case 11: hipLaunchKernelGGL(k_hist_scan<11>, dim3(P), dim3(256), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 4: hipLaunchKernelGGL(k_hist_scan<4>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 8: hipLaunchKernelGGL(k_hist_scan<8>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 9: hipLaunchKernelGGL(k_hist_scan<9>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 11: hipLaunchKernelGGL(k_hist_scan<11>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     SA_HIP(hipGetLastError());
@@ -378,12 +397,14 @@ int sort_run(const SortBufs &b, int cur, const uint32_t *count_dev, int64_t n, i
         const int width = (bits - lo) < t.dbits ? (bits - lo) : t.dbits;
         const uint32_t shift = uint32_t(bit_lo + lo);
         const uint32_t dmask = (1u << width) - 1u;
-        TimedScope ts("radix_pass", double(n) * 24.0, s);
+        TimedScope ts = count_dev ? TimedScope("radix_pass", 0.0, 24.0, s)
+                                  : TimedScope("radix_pass", double(n) * 24.0, s);
         int rc = SA_OK;
         uint32_t *fl = b.flags + size_t(p) * tiles * R;
         switch (t.dbits) {
             case 4: rc = launch_pass_d<4>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
             case 8: rc = launch_pass_d<8>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
+            case 9: rc = launch_pass_d<9>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
             case 11: rc = launch_pass_d<11>(t, n, s, b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], count_dev, uint32_t(n), shift, dmask, b.gbase + p * R, fl, b.tickets + p, b.err); break;
             default: rc = fail(SA_ERR_INVALID, "unsupported digit width");
         }
@@ -467,6 +488,7 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
     switch (t.dbits) {
         case 4: hipLaunchKernelGGL(k_key0<4>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
         case 8: hipLaunchKernelGGL(k_key0<8>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 9: hipLaunchKernelGGL(k_key0<9>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
         case 11: hipLaunchKernelGGL(k_key0<11>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
@@ -582,10 +604,12 @@ int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, const SortB
     SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     size_t lds = size_t(P) * t.radix() * 4;
-    TimedScope ts("keybuild", double(n) * 4.0, s);
+    // every position's label is read; each active one adds rank[p+h] and its key and value
+    TimedScope ts("keybuild", double(n) * 4.0, 16.0, s);
     switch (t.dbits) {
         case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
         case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
+        case 9: hipLaunchKernelGGL(k_keys_dbl<9>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
         case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }

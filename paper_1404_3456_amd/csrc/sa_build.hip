@@ -22,6 +22,7 @@
 // concatenation, with each text's index placed above the first-round key: every text's
 // suffixes then form one block of the order, labels of different texts never mix, and the
 // block of text s is exactly the suffix array of text s (in concatenated coordinates).
+#include <cstring>
 #include <vector>
 
 #include "device.hpp"
@@ -157,6 +158,15 @@ __global__ void k_round_end(uint32_t *state, uint32_t h_first) {
     state[kStActive] = state[kStNext];
 }
 
+// Adds a block's offset to suffix-array and inverse entries built for that block alone.
+__global__ __launch_bounds__(256) void k_add_offset(int32_t *__restrict__ sa, int32_t *__restrict__ isa,
+                                                    int64_t n, int32_t base) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    sa[i] += base;
+    if (isa) isa[i] += base;
+}
+
 __global__ __launch_bounds__(256) void k_strip(uint32_t *__restrict__ rank, uint32_t n) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) rank[i] &= kRankMask;
@@ -213,7 +223,8 @@ static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     // algorithmic bytes: read K (8) + V (4) + S (4 when present); write sa (4) + rank (4) +
     // S_new (4, upper bound)
-    TimedScope ts("rank_update", double(a_bound) * (S ? 28.0 : 24.0), s);
+    TimedScope ts = S ? TimedScope("rank_update", 0.0, 28.0, s)
+                      : TimedScope("rank_update", double(a_bound) * 24.0, s);
     hipLaunchKernelGGL(k_rank_update, dim3(unsigned(tiles)), dim3(kRuBlock), 0, s, K, V, S,
                        uint32_t(n), int(round0), uint32_t(h0), rbits, sa, rank, S_new, lbflags,
                        tick, state, state + kStErr);
@@ -227,6 +238,23 @@ static int check_err(uint32_t e) {
     if (e & kErrNoSepEnd) return fail(SA_ERR_INVALID, "every text must end with '$'");
     if (e) return fail(SA_ERR_HIP, "device consistency check failed (code " + std::to_string(e) + ")");
     return SA_OK;
+}
+
+// Pinned host words and events for reading round state without a full stream sync (one set
+// per host thread; two slots so one round's state can be in flight while the other is read).
+struct PinnedState {
+    uint32_t *h = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ok = false;
+    PinnedState() {
+        ok = hipHostMalloc(reinterpret_cast<void **>(&h), 64, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) == hipSuccess;
+    }
+};
+static PinnedState &pinned_state() {
+    static thread_local PinnedState ps;
+    return ps;
 }
 
 // One suffix-array build (plain: one text; batched: n_sets texts, set_off_h on the host).
@@ -243,6 +271,13 @@ struct Build {
     int h0 = kH0;
     int key0_bits = 2 * kH0 + 5;
     int rbits = 1;
+
+    // copies the 8 state words to pinned slot k and records its event (stream order)
+    int snapshot(PinnedState &ps, int k) {
+        SA_HIP(hipMemcpyAsync(ps.h + 8 * k, L.state, 32, hipMemcpyDeviceToHost, s));
+        SA_HIP(hipEventRecord(ps.ev[k], s));
+        return SA_OK;
+    }
 
     int read_state(uint32_t host[8]) {
         SA_HIP(hipMemcpyAsync(host, L.state, 32, hipMemcpyDeviceToHost, s));
@@ -295,64 +330,89 @@ struct Build {
         rbits = bits_for(n - 1);
         SA_TRY(round0());
         uint32_t host[8];
-        SA_TRY(read_state(host));
-        SA_TRY(check_err(host[kStErr]));
-        int64_t A = host[kStActive];
-        int sl = 0;
-        if (use_graph && A > 0) {
-            // Record two rounds (the slot buffers alternate) once and replay until done.
-            const int64_t bound = A;
-            hipGraph_t graph = nullptr;
-            hipGraphExec_t exec = nullptr;
-            // Capture on a private stream (the caller's may be the legacy default stream,
-            // which cannot be captured); the graph is then launched on the caller's stream.
-            hipStream_t cap = nullptr;
-            SA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            const hipStream_t caller = s;
-            s = cap;
-            timing_pause(true);
-            hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            int rc = be == hipSuccess ? SA_OK : fail(SA_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(be));
-            if (rc == SA_OK) rc = doubling_round(0, bound);
-            if (rc == SA_OK) rc = doubling_round(1, bound);
-            hipError_t ce = be == hipSuccess ? hipStreamEndCapture(cap, &graph) : hipSuccess;
-            timing_pause(false);
-            s = caller;
-            hipStreamDestroy(cap);
-            if (rc != SA_OK) {
-                if (graph) hipGraphDestroy(graph);
-                return rc;
-            }
-            SA_HIP(ce);
-            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
-            SA_HIP(ie);
-            int guard = 0;
-            while (A > 0) {
-                if (++guard > 40) {
-                    hipGraphExecDestroy(exec);
-                    return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
+        if (use_graph) {
+            SA_TRY(read_state(host));
+            SA_TRY(check_err(host[kStErr]));
+            int64_t A = host[kStActive];
+            if (A > 0) {
+                // Record two rounds (the slot buffers alternate) once and replay until done.
+                // Capture on a private stream (the caller's may be the legacy default stream,
+                // which cannot be captured); the graph is then launched on the caller's stream.
+                const int64_t bound = A;
+                hipGraph_t graph = nullptr;
+                hipGraphExec_t exec = nullptr;
+                hipStream_t cap = nullptr;
+                SA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+                const hipStream_t caller = s;
+                s = cap;
+                timing_pause(true);
+                hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+                int rc = be == hipSuccess ? SA_OK : fail(SA_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(be));
+                if (rc == SA_OK) rc = doubling_round(0, bound);
+                if (rc == SA_OK) rc = doubling_round(1, bound);
+                hipError_t ce = be == hipSuccess ? hipStreamEndCapture(cap, &graph) : hipSuccess;
+                timing_pause(false);
+                s = caller;
+                hipStreamDestroy(cap);
+                if (rc != SA_OK) {
+                    if (graph) hipGraphDestroy(graph);
+                    return rc;
                 }
-                hipError_t le = hipGraphLaunch(exec, s);
-                if (le != hipSuccess) {
-                    hipGraphExecDestroy(exec);
-                    SA_HIP(le);
+                SA_HIP(ce);
+                hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                SA_HIP(ie);
+                int guard = 0;
+                while (A > 0) {
+                    if (++guard > 40) {
+                        hipGraphExecDestroy(exec);
+                        return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
+                    }
+                    hipError_t le = hipGraphLaunch(exec, s);
+                    if (le != hipSuccess) {
+                        hipGraphExecDestroy(exec);
+                        SA_HIP(le);
+                    }
+                    int rr = read_state(host);
+                    if (rr != SA_OK) { hipGraphExecDestroy(exec); return rr; }
+                    if (host[kStErr]) { hipGraphExecDestroy(exec); return check_err(host[kStErr]); }
+                    A = host[kStActive];
                 }
-                int rr = read_state(host);
-                if (rr != SA_OK) { hipGraphExecDestroy(exec); return rr; }
-                if (host[kStErr]) { hipGraphExecDestroy(exec); return check_err(host[kStErr]); }
-                A = host[kStActive];
+                SA_HIP(hipGraphExecDestroy(exec));
             }
-            SA_HIP(hipGraphExecDestroy(exec));
         } else {
-            while (A > 0) {
-                if (host[kStRounds] > 40) return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
-                SA_TRY(doubling_round(sl, A));
-                SA_TRY(read_state(host));
-                SA_TRY(check_err(host[kStErr]));
-                if (int64_t(host[kStKeys]) != A) return fail(SA_ERR_HIP, "sa_build: active-suffix count mismatch");
-                A = host[kStActive];
+            // One round ahead: round r+1 is enqueued before the host looks at the state round r
+            // left (copied to pinned memory behind an event), so the readback overlaps device
+            // work.  A round enqueued after the last useful one finds no active suffix and every
+            // kernel of it returns at once.  A round's bounds (grid and fill sizes) use the last
+            // count the host has seen, which can only be larger than the true one.
+            PinnedState &ps = pinned_state();
+            if (!ps.ok) return fail(SA_ERR_HIP, "sa_build: no pinned host memory for round state");
+            int cur = 0, sl = 0;
+            int64_t bound = n;
+            SA_TRY(snapshot(ps, cur));  // state after round 0
+            for (int guard = 0;; ++guard) {
+                if (guard > 40) return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
+                const int64_t tag = timing_round_begin();
+                SA_TRY(doubling_round(sl, bound));
+                SA_TRY(snapshot(ps, cur ^ 1));
                 sl ^= 1;
+                SA_HIP(hipEventSynchronize(ps.ev[cur]));
+                memcpy(host, ps.h + 8 * cur, sizeof(uint32_t) * 8);
+                // the state before the round just enqueued holds that round's active count
+                timing_round_items(tag, host[kStActive]);
+                timing_poll();
+                SA_TRY(check_err(host[kStErr]));
+                cur ^= 1;
+                if (host[kStActive] == 0) {
+                    // the round just enqueued is a no-op; wait for it so the stream is clean
+                    SA_HIP(hipEventSynchronize(ps.ev[cur]));
+                    memcpy(host, ps.h + 8 * cur, sizeof(uint32_t) * 8);
+                    timing_flush();
+                    SA_TRY(check_err(host[kStErr]));
+                    break;
+                }
+                bound = host[kStActive];
             }
         }
         if (rounds_out) *rounds_out = int(host[kStRounds]);
@@ -423,13 +483,55 @@ extern "C" int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *is
                         stream, need);
 }
 
-extern "C" int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const sa_tuning *tune) {
+// Groups of consecutive texts with at most `pack` characters each (a text longer than `pack`
+// forms a group of its own); pack <= 0 puts every text in one group.  Returns group bounds.
+static std::vector<int32_t> pack_groups(const int64_t *off, int32_t n_sets, int64_t pack) {
+    std::vector<int32_t> g{0};
+    if (pack <= 0) {
+        g.push_back(n_sets);
+        return g;
+    }
+    int32_t start = 0;
+    for (int32_t s = 0; s < n_sets; ++s) {
+        if (s > start && off[s + 1] - off[start] > pack) {
+            g.push_back(s);
+            start = s;
+        }
+    }
+    g.push_back(n_sets);
+    return g;
+}
+
+static int resolve_batched(const sa_tuning *tune, Tune *t, int64_t *pack) {
+    sa_tuning copy{};
+    if (tune) copy = *tune;
+    *pack = copy.seg_pack;
+    copy.seg_pack = 0;
+    if (*pack < 0) return fail(SA_ERR_INVALID, "seg_pack must be >= 0");
+    return resolve_tuning(&copy, t);
+}
+
+extern "C" int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const int64_t *set_off_h,
+                                             const sa_tuning *tune) {
     Tune t;
-    if (n < 1 || n_sets < 1 || resolve_tuning(tune, &t) != SA_OK) return -1;
-    Carver c(nullptr, INT64_MAX);
-    BuildLayout L;
-    carve_build(c, n, n_sets, t, &L);
-    return c.off + 256;
+    int64_t pack = 0;
+    if (n < 1 || n_sets < 1 || resolve_batched(tune, &t, &pack) != SA_OK) return -1;
+    int64_t need = 0;
+    if (pack > 0 && set_off_h) {
+        std::vector<int32_t> g = pack_groups(set_off_h, n_sets, pack);
+        for (size_t k = 0; k + 1 < g.size(); ++k) {
+            Carver c(nullptr, INT64_MAX);
+            BuildLayout L;
+            carve_build(c, set_off_h[g[k + 1]] - set_off_h[g[k]], g[k + 1] - g[k], t, &L);
+            need = c.off > need ? c.off : need;
+        }
+    } else {
+        Carver c(nullptr, INT64_MAX);
+        BuildLayout L;
+        carve_build(c, n, n_sets, t, &L);
+        need = c.off;
+    }
+    return need + 256;
 }
 
 extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h,
@@ -444,8 +546,31 @@ extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *s
     for (int32_t i = 0; i < n_sets; ++i)
         if (set_off_h[i + 1] <= set_off_h[i])
             return fail(SA_ERR_INVALID, "sa_build_batched: every text must be non-empty");
-    const int64_t need = sa_build_batched_ws_bytes(n, n_sets, tune);
+    Tune t;
+    int64_t pack = 0;
+    SA_TRY(resolve_batched(tune, &t, &pack));
+    const int64_t need = sa_build_batched_ws_bytes(n, n_sets, set_off_h, tune);
     if (need < 0) return fail(SA_ERR_INVALID, "sa_build_batched: bad tuning");
-    return build_common(text, n, set_off_h, n_sets, sa, isa_or_null, ws, ws_bytes, tune,
-                        use_graph != 0, rounds_h, stream, need);
+    sa_tuning inner{t.dbits, t.block, t.items, 0};
+    std::vector<int32_t> g = pack_groups(set_off_h, n_sets, pack);
+    int32_t rounds_max = 0;
+    for (size_t k = 0; k + 1 < g.size(); ++k) {
+        const int32_t s0 = g[k], s1 = g[k + 1];
+        const int64_t base = set_off_h[s0], len = set_off_h[s1] - base;
+        std::vector<int64_t> local(size_t(s1 - s0) + 1);
+        for (int32_t s = s0; s <= s1; ++s) local[size_t(s - s0)] = set_off_h[s] - base;
+        int32_t r = 0;
+        SA_TRY(build_common(text + base, len, local.data(), s1 - s0, sa + base,
+                            isa_or_null ? isa_or_null + base : nullptr, ws, ws_bytes, &inner,
+                            use_graph != 0, &r, stream, need));
+        if (base > 0) {
+            hipLaunchKernelGGL(k_add_offset, dim3(unsigned((len + 255) / 256)), dim3(256), 0, stream,
+                               sa + base, isa_or_null ? isa_or_null + base : nullptr, len,
+                               int32_t(base));
+            SA_HIP(hipGetLastError());
+        }
+        rounds_max = r > rounds_max ? r : rounds_max;
+    }
+    if (rounds_h) *rounds_h = rounds_max;
+    return SA_OK;
 }

@@ -91,7 +91,10 @@ struct Batch;
 
 struct Job {
     uint64_t id = 0;
-    std::vector<uint8_t> text;
+    std::vector<uint8_t> text;       // owned copy (default)
+    const uint8_t *borrowed = nullptr;  // caller's text (ASM_BORROW), valid until done
+    bool checked = false;            // alphabet validated and reads counted
+    const uint8_t *data() const { return borrowed ? borrowed : text.data(); }
     int32_t min_len = 1;
     int64_t n = 0, m = 0;
     int status = SA_PENDING;
@@ -144,7 +147,7 @@ static int64_t job_keep_bytes(int64_t n) { return 13 * n + 4 * 256; }
 
 // scratch a batch needs while it runs (the build workspace dominates)
 static int64_t batch_scratch_bytes(int64_t n, int n_jobs) {
-    int64_t b = sa_build_batched_ws_bytes(n, n_jobs, nullptr);
+    int64_t b = sa_build_batched_ws_bytes(n, n_jobs, nullptr, nullptr);
     int64_t l = sa_lcp_ws_bytes(n);
     return (b > l ? b : l) + 4096;
 }
@@ -202,6 +205,21 @@ __global__ void k_rows_shift(int32_t *__restrict__ rows, int64_t nrows,
     rows[3 * i + 1] -= int32_t(read_lo[lo]);
 }
 
+// One branch-free pass (vectorisable): count separators, flag any byte outside A,C,G,T,$.
+static bool scan_text(const uint8_t *t, int64_t n, int64_t *m_out) {
+    int64_t m = 0;
+    uint32_t bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint8_t c = t[i];
+        const uint32_t sep = c == '$';
+        const uint32_t base = (c == 'A') | (c == 'C') | (c == 'G') | (c == 'T');
+        m += sep;
+        bad |= (sep | base) ^ 1u;
+    }
+    *m_out = m;
+    return bad == 0;
+}
+
 static int64_t arena_alloc(asm_server *S, int64_t bytes) {
     std::lock_guard<std::mutex> lk(S->mu);
     return S->arena.alloc(bytes);
@@ -227,7 +245,7 @@ static int run_batch(asm_server *S, std::vector<Job *> &js, Batch *B, hipStream_
     o += (4 * n + 255) & ~int64_t(255);
     B->lcp = reinterpret_cast<int32_t *>(mem + o);
     for (int j = 0; j < nj; ++j)
-        SA_HIP(hipMemcpyAsync(text + off[j], js[j]->text.data(), size_t(js[j]->n), hipMemcpyHostToDevice, s));
+        SA_HIP(hipMemcpyAsync(text + off[j], js[j]->data(), size_t(js[j]->n), hipMemcpyHostToDevice, s));
     int64_t scr_bytes = batch_scratch_bytes(n, nj);
     char *scr = S->arena.ptr(scratch[0]);
     int32_t rounds = 0;
@@ -360,14 +378,38 @@ static void worker_main(asm_server *S) {
             ++S->concurrent_now;
             if (S->concurrent_now > S->concurrent_max) S->concurrent_max = S->concurrent_now;
         }
-        int rc = run_batch(S, js, B, s, scratch);
+        // borrowed texts are validated here, off the submitting thread
+        std::vector<Job *> rejected;
+        for (size_t k = 0; k < js.size();) {
+            Job *j = js[k];
+            if (!j->checked) {
+                int64_t m = 0;
+                const bool ok = scan_text(j->data(), j->n, &m);
+                j->m = m;
+                j->checked = true;
+                if (!ok) {
+                    rejected.push_back(j);
+                    js.erase(js.begin() + long(k));
+                    continue;
+                }
+            }
+            ++k;
+        }
+        int rc = js.empty() ? SA_OK : run_batch(S, js, B, s, scratch);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             --S->concurrent_now;
             ++S->batches;
             for (int64_t a : scratch) S->arena.release(a);
             const double t = now_s(S);
-            if (rc != SA_OK) {
+            for (Job *j : rejected) {
+                j->status = SA_ERR_ALPHABET;
+                j->t_done = t;
+                j->batch = nullptr;
+                --B->refs;
+                ++S->jobs_done;
+            }
+            if (rc != SA_OK || js.empty()) {
                 S->arena.release(B->mem_off);
                 if (B->rows_off >= 0) S->arena.release(B->rows_off);
                 delete B;
@@ -377,6 +419,7 @@ static void worker_main(asm_server *S) {
                 j->t_done = t;
                 if (rc != SA_OK) j->batch = nullptr;
                 std::vector<uint8_t>().swap(j->text);
+                j->borrowed = nullptr;
                 ++S->jobs_done;
             }
         }
@@ -417,28 +460,28 @@ extern "C" int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_j
 }
 
 extern "C" int asm_submit(asm_server *S, const uint8_t *text_h, int64_t n, int32_t min_len,
-                          uint64_t *job_id_h) {
+                          int32_t flags, uint64_t *job_id_h) {
     if (!S || !text_h || !job_id_h) return fail(SA_ERR_INVALID, "asm_submit: NULL pointer");
     if (n < 1 || min_len < 1) return fail(SA_ERR_INVALID, "asm_submit: need n >= 1, min_len >= 1");
+    if (flags & ~ASM_BORROW) return fail(SA_ERR_INVALID, "asm_submit: unknown flags");
     if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "asm_submit: n >= 2^31-2");
     if (text_h[n - 1] != '$') return fail(SA_ERR_INVALID, "asm_submit: text must end with '$'");
-    // one branch-free pass (vectorisable): count separators, flag any other byte
-    int64_t m = 0;
-    uint32_t bad = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const uint8_t c = text_h[i];
-        const uint32_t sep = c == '$';
-        const uint32_t base = (c == 'A') | (c == 'C') | (c == 'G') | (c == 'T');
-        m += sep;
-        bad |= (sep | base) ^ 1u;
-    }
-    if (bad) return fail(SA_ERR_ALPHABET, "asm_submit: text holds a byte other than A, C, G, T, $");
     if (job_keep_bytes(n) + batch_scratch_bytes(n, 1) > S->arena.capacity())
         return fail(SA_ERR_NOMEM, "asm_submit: job larger than the server's memory budget");
     Job *j = new Job;
-    j->text.assign(text_h, text_h + n);
+    if (flags & ASM_BORROW) {
+        j->borrowed = text_h;  // validated by the worker that runs it
+    } else {
+        int64_t m = 0;
+        if (!scan_text(text_h, n, &m)) {
+            delete j;
+            return fail(SA_ERR_ALPHABET, "asm_submit: text holds a byte other than A, C, G, T, $");
+        }
+        j->text.assign(text_h, text_h + n);
+        j->m = m;
+        j->checked = true;
+    }
     j->n = n;
-    j->m = m;
     j->min_len = min_len;
     {
         std::lock_guard<std::mutex> lk(S->mu);

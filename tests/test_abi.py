@@ -73,6 +73,7 @@ def test_host_argument_checks_without_gpu():
                            dummy, 1 << 20, None, None) == _abi.SA_ERR_INVALID
     assert lib.sa_lcp(dummy, 100, dummy, None, dummy, dummy, 1 << 20, None) == _abi.SA_ERR_INVALID
     assert lib.sa_lcp_set_chunk(0) == _abi.SA_ERR_INVALID
+    assert lib.sa_lcp_set_chunk(3) == _abi.SA_ERR_INVALID
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -87,7 +87,7 @@ def test_pack_rejects_bad_text(lib):
 
 # ---- radix sort: one pass is a stable counting sort; the whole sort is a stable sort ---------
 
-@pytest.mark.parametrize("tuning", [None, {"digit_bits": 4}, {"digit_bits": 11},
+@pytest.mark.parametrize("tuning", [None, {"digit_bits": 4}, {"digit_bits": 9}, {"digit_bits": 11},
                                     {"block_threads": 512, "items_per_thread": 8},
                                     {"block_threads": 256, "items_per_thread": 8}])
 @pytest.mark.parametrize("bits", [(0, 64), (0, 8), (3, 14), (32, 49), (60, 64)])
@@ -194,7 +194,7 @@ def test_small_plain_workload(lib):
 
 
 TUNINGS = [{"digit_bits": d, "block_threads": b, "items_per_thread": i}
-           for d in (4, 8, 11) for b, i in ((256, 8), (256, 16), (512, 8), (512, 16))]
+           for d in (4, 8, 9, 11) for b, i in ((256, 8), (256, 16), (512, 8), (512, 16))]
 
 
 def test_tunings_identical(lib):
@@ -272,3 +272,27 @@ def test_batched_rejects_bad_offsets(lib):
         lib.sa_build_batched(dev(cat), bad)
     with pytest.raises(lib.SaasmError):
         lib.sa_build_batched(dev(cat), off[:-1])
+
+
+def test_batched_seg_pack_identical(lib):
+    """Packing texts into several builds (seg_pack) gives the same arrays as one build."""
+    texts, off, cat = _batched_case(12, 40, 500, 8000)
+    t = dev(cat)
+    sa1, isa1 = lib.sa_build_batched(t, off)
+    for pack in (1, 20_000, 100_000):
+        sa2, isa2 = lib.sa_build_batched(t, off, tuning={"seg_pack": pack}, use_graph=(pack != 1))
+        assert torch.equal(sa1, sa2) and torch.equal(isa1, isa2), pack
+    assert lib.sa_build_batched_ws_bytes(cat.size, 40, {"seg_pack": 20_000}, off) < \
+        lib.sa_build_batched_ws_bytes(cat.size, 40)
+
+
+def test_autotune_picks_a_valid_tuning(lib, tmp_path):
+    from paper_1404_3456_amd import autotune
+    t = dev(synth.genome_reads(5, 30_000, 1000, 150, err=0.005))
+    tu, rep = autotune.autotune(t, candidates=[(8, 512, 16), (9, 256, 16)], reps=1,
+                                cache_path=str(tmp_path / "cache.json"))
+    assert rep["cached"] is False and len(rep["tried"]) == 2
+    tu2, rep2 = autotune.autotune(t, cache_path=str(tmp_path / "cache.json"))
+    assert rep2["cached"] is True and tu2 == tu
+    sa, _ = lib.sa_build(t, tuning=tu)
+    assert np.array_equal(sa.cpu().numpy(), oracle.suffix_array(t.cpu().numpy()))

@@ -113,3 +113,22 @@ def test_injected_alloc_failure_fails_one_batch_only(pkg):
             srv.asm_release(jid)
         srv.asm_release(first)
         assert srv.asm_server_stats()["arena_used"] == 0
+
+
+def test_borrowed_texts_and_deferred_rejection(pkg):
+    texts = jobs_pool(6, seed=21)
+    bad = np.frombuffer(b"ACGTN$ACG$", dtype=np.uint8).copy()
+    with pkg.AsmServer(1 << 30, max_jobs_per_batch=8, workers=2) as srv:
+        ids = [srv.asm_submit(t, 20, borrow=True) for t in texts[:3]]
+        bad_id = srv.asm_submit(bad, 3, borrow=True)  # accepted, fails when run
+        ids += [srv.asm_submit(t, 20, borrow=True) for t in texts[3:]]
+        assert wait(srv, bad_id)["status"] == pkg.SA_ERR_ALPHABET
+        for jid, t in zip(ids, texts):
+            r = wait(srv, jid)
+            assert r["status"] == 0
+            sa, isa, lcp, ovl = host(r)
+            assert np.array_equal(sa, oracle.suffix_array(t))
+            assert np.array_equal(ovl, oracle.overlaps(t, 20))
+            srv.asm_release(jid)
+        srv.asm_release(bad_id)
+        assert srv.asm_server_stats()["arena_used"] == 0
