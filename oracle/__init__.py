@@ -56,6 +56,8 @@ def _load():
         lib.oracle_num_reads.restype = I64
         lib.oracle_check_adjacent.argtypes = [P, I64, P, P, P, I64, P, ctypes.c_int]
         lib.oracle_check_adjacent.restype = I64
+        lib.oracle_lookup.argtypes = [P, I64, P, P, I64, P, ctypes.c_int]
+        lib.oracle_lookup.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -149,3 +151,20 @@ def check_adjacent(text, sa, lcp, idx, nthreads=None):
     bad = _load().oracle_check_adjacent(_ptr(t), t.size, _ptr(sa), lp, _ptr(idx), idx.size,
                                         ctypes.byref(first), _threads(nthreads))
     return int(bad), int(first.value)
+
+
+def lookup(text, patterns, nthreads=None) -> np.ndarray:
+    """SA interval [lo, hi) of the suffixes that start with each pattern, from the definition
+    over text positions (no suffix array): (k, 2) int64.  `patterns` is a list of byte strings
+    without separators."""
+    t = _text(text)
+    pats = [bytes(p) for p in patterns]
+    off = np.zeros(len(pats) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(p) for p in pats])
+    buf = np.frombuffer(b"".join(pats) + b"\0", dtype=np.uint8).copy()
+    out = np.zeros((max(len(pats), 1), 2), dtype=np.int64)
+    rc = _load().oracle_lookup(_ptr(t), t.size, _ptr(buf), _ptr(off), len(pats), _ptr(out),
+                               _threads(nthreads))
+    if rc != 0:
+        raise ValueError("pattern holds a separator, or bad text")
+    return out[: len(pats)]

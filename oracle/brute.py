@@ -57,3 +57,16 @@ def overlaps(text: bytes, min_len: int):
             if best:
                 out.append((a, b, best))
     return out
+
+
+def lookup(text: bytes, pattern: bytes):
+    """[lo, hi): the positions of the literal suffix array whose suffixes start with pattern
+    (the pattern's bytes mapped like the text's non-separator bytes)."""
+    s = to_ints(text)
+    m = text.count(b"$")
+    pat = [m + v for v in pattern]
+    hits = [i for i, p in enumerate(suffix_array(text)) if s[p:p + len(pat)] == pat]
+    if not hits:  # empty interval: its place is the number of smaller suffixes
+        lo = sum(1 for p in range(len(s)) if s[p:] < pat)
+        return lo, lo
+    return hits[0], hits[-1] + 1

@@ -21,6 +21,12 @@
  *  LCP.  lcp[0] = 0; lcp[i] = length of the longest common prefix of the suffixes at sa[i-1]
  *  and sa[i].  Two separators never match each other (they are different symbols).
  *
+ *  Lookup.  For a pattern P (bytes other than the separator), the suffixes that start with P
+ *  are one interval [lo, hi) of the SA (Sec. IV: the array is searched to decide whether one
+ *  string is a prefix of another).  By definition lo is the number of suffixes that sort
+ *  below P without starting with it, and hi - lo is the number of text positions where P
+ *  occurs; both are counted over text positions, without any suffix array.
+ *
  *  Overlaps.  For every ordered pair of distinct reads (a, b), the largest l with
  *  min_len <= l <= min(|a|, |b|) such that the last l bytes of a equal the first l bytes of b;
  *  reported as (a, b, l) when such l exists, sorted by (a, b).  l = |a| is the paper's 'fir'
@@ -359,4 +365,45 @@ int64_t oracle_check_adjacent(const uint8_t *t, int64_t n, const int32_t *sa, co
     }
     if (first_bad) *first_bad = first;
     return bad;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Pattern lookup: the SA interval of the suffixes that start with a pattern (see header).   */
+/* ---------------------------------------------------------------------------------------- */
+
+/* -1: suffix p sorts below P and does not start with it; 0: it starts with P; +1: above. */
+static int suffix_vs_pattern(const uint8_t *t, int64_t p, const uint8_t *pat, int64_t m)
+{
+    for (int64_t k = 0; k < m; ++k) {
+        uint8_t x = t[p + k];
+        if (x == SEPB) return -1;  /* the suffix ends first: a separator is below every byte */
+        if (x != pat[k]) return (x < pat[k]) ? -1 : 1;
+    }
+    return 0;
+}
+
+/* Patterns are pats[off[i] .. off[i+1]) for i < npat; lohi[2i], lohi[2i+1] receive [lo, hi).
+ * Returns 0, or -1 for a pattern holding a separator or a bad text. */
+int oracle_lookup(const uint8_t *t, int64_t n, const uint8_t *pats, const int64_t *off,
+                  int64_t npat, int64_t *lohi, int nthreads)
+{
+    if (text_ok(t, n) != 0) return -1;
+    for (int64_t i = 0; i < npat; ++i)
+        for (int64_t k = off[i]; k < off[i + 1]; ++k)
+            if (pats[k] == SEPB) return -1;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int64_t i = 0; i < npat; ++i) {
+        const uint8_t *pat = pats + off[i];
+        const int64_t m = off[i + 1] - off[i];
+        int64_t below = 0, occ = 0;
+        for (int64_t p = 0; p < n; ++p) {
+            const int c = suffix_vs_pattern(t, p, pat, m);
+            if (c < 0) ++below;
+            else if (c == 0) ++occ;
+        }
+        lohi[2 * i] = below;
+        lohi[2 * i + 1] = below + occ;
+    }
+    return 0;
 }

@@ -113,11 +113,8 @@ void timing_round_items(int64_t tag, int64_t items) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &p : g_pending) {
         if (p.tag != tag) continue;
-        if (items <= 0) {
-            p.bytes = -1.0;  // empty round: dropped when resolved
-        } else {
-            p.bytes += p.per_item * double(items);
-        }
+        // an empty round still launched its kernels (they exit at once): timed, no bytes
+        p.bytes = items <= 0 ? 0.0 : p.bytes + p.per_item * double(items);
         p.tag = -1;
     }
 }
@@ -137,8 +134,11 @@ static void timing_resolve(bool block) {
             g_pending[keep++] = p;
             continue;
         }
+        // a launch whose round count never arrived belongs to a round the build did not need
+        // (it found nothing active): timed, no bytes
+        if (p.tag >= 0) p.bytes = 0.0;
         float ms = 0.f;
-        if (p.tag < 0 && p.bytes >= 0.0 && hipEventSynchronize(p.b) == hipSuccess &&
+        if (hipEventSynchronize(p.b) == hipSuccess &&
             hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             Acc &a = g_acc[p.key];
             a.launches += 1;

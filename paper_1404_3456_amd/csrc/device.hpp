@@ -64,21 +64,27 @@ __device__ __forceinline__ uint32_t lb32_word(bool inclusive, uint32_t count) {
 }
 
 // Exclusive prefix of this tile's count for one digit, summed over all earlier tiles.  The
-// flags of tile p for digit d live at flags[p * stride + d].
+// flags of tile p for digit d live at flags[p * stride + d].  The words of kLbWin earlier tiles
+// are requested together, so one walk step costs one memory latency, not kLbWin of them.
+constexpr int kLbWin = 4;
 __device__ __forceinline__ uint32_t lookback_digit(const uint32_t *flags, int tile, uint32_t stride,
                                                    uint32_t d, uint32_t *err) {
-    uint32_t excl = 0;
-    for (int p = tile - 1; p >= 0; --p) {
-        const uint32_t *f = flags + size_t(p) * stride + d;
-        uint32_t v = ld_agent(f);
-        uint32_t spins = 0;
-        while (v == 0) {
-            if (++spins > kSpinLimit) { raise_err(err, kErrSpin); v = kLb32Inc | 1u; break; }
-            __builtin_amdgcn_s_sleep(1);
-            v = ld_agent(f);
+    uint32_t excl = 0, spins = 0;
+    for (int p = tile - 1; p >= 0; p -= kLbWin) {
+        uint32_t v[kLbWin];
+#pragma unroll
+        for (int i = 0; i < kLbWin; ++i)  // tile -1 and before: an inclusive zero, never reached
+            v[i] = p - i >= 0 ? ld_agent(flags + size_t(p - i) * stride + d) : (kLb32Inc | 1u);
+#pragma unroll
+        for (int i = 0; i < kLbWin; ++i) {
+            while (v[i] == 0) {  // tile p - i has not published yet
+                if (++spins > kSpinLimit) { raise_err(err, kErrSpin); v[i] = kLb32Inc | 1u; break; }
+                __builtin_amdgcn_s_sleep(1);
+                v[i] = ld_agent(flags + size_t(p - i) * stride + d);
+            }
+            excl += (v[i] & ~kLb32Inc) - 1u;
+            if (v[i] & kLb32Inc) return excl;
         }
-        excl += (v & ~kLb32Inc) - 1u;
-        if (v & kLb32Inc) break;
     }
     return excl;
 }
@@ -129,20 +135,16 @@ __device__ uint64_t lookback_tile(uint64_t *flags, int tile, uint64_t agg, uint3
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        // combine lanes 0..first_inc (or all 64) from the latest tile backwards: the payload of
-        // lane l is later in text order than that of lane l+1.
-        uint64_t val = (int(lane) <= first_inc) ? (v & kLb64Val) : 0;
-        bool use = int(lane) <= first_inc;
-        // serial fold over <= 64 lanes via readlane: earlier tiles have larger lane index
-        uint64_t acc = 0;
-        bool acc_set = false;
-        int top = first_inc < 63 ? first_inc : 63;
-        for (int l = top; l >= 0; --l) {
-            uint64_t x = __shfl(val, l);
-            if (!acc_set) { acc = x; acc_set = true; }
-            else acc = Op::combine(acc, x);
+        // Combine lanes 0..first_inc (or all 64): the payload of lane l is later in text order
+        // than that of lane l+1.  Lanes past first_inc contribute the identity (0 for both
+        // operators), so a tree over all 64 lanes leaves the ordered combination in lane 0.
+        uint64_t x = (int(lane) <= first_inc) ? (v & kLb64Val) : 0;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint64_t y = __shfl_down(x, o);  // lanes l+o.. : earlier tiles
+            x = (int(lane) + o < kWave) ? Op::combine(y, x) : x;
         }
-        (void)use;
+        const uint64_t acc = __shfl(x, 0);
         excl = have ? Op::combine(acc, excl) : acc;
         have = true;
         if (first_inc < 64) break;

@@ -13,25 +13,35 @@
 
 namespace saasm {
 
-// 32 bases starting at position a, base 0 in bits 63..62.
-__device__ __forceinline__ uint64_t window64(const uint32_t *__restrict__ packed, uint32_t a) {
-    const uint32_t w = a >> 4, o = a & 15;
-    uint64_t x = (uint64_t(packed[w]) << 32) | packed[w + 1];
-    x <<= 2 * o;
-    if (o) x |= uint64_t(packed[w + 2]) >> (32 - 2 * o);
-    return x;
+// Text blocks for random-access windows: record b holds the packed codes of positions
+// 32b .. 32b+31 (two words, position 32b in the top bits of the first) and their separator
+// bits (position 32b in bit 31), padded to 16 bytes, so a 32-position window starting anywhere
+// is two aligned 16-byte loads instead of five scattered word loads.
+__global__ __launch_bounds__(256) void k_blocks(const uint32_t *__restrict__ packed,
+                                                const uint32_t *__restrict__ sepmask,
+                                                uint4 *__restrict__ blk, int64_t nrec) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nrec) return;
+    blk[b] = make_uint4(packed[2 * b], packed[2 * b + 1], sepmask[b], 0u);
 }
 
-// Separator bits of positions a .. a+31, position a in bit 31.
-__device__ __forceinline__ uint32_t sepwin32(const uint32_t *__restrict__ sepmask, uint32_t a) {
-    const uint32_t w = a >> 5, o = a & 31;
-    const uint64_t x = (uint64_t(sepmask[w]) << 32) | sepmask[w + 1];
-    return uint32_t((x << o) >> 32);
+struct Window {
+    uint64_t code;  // 32 bases from position a, base a in bits 63..62
+    uint32_t sep;   // separator bits of positions a .. a+31, position a in bit 31
+};
+
+__device__ __forceinline__ Window window_at(const uint4 *__restrict__ blk, uint32_t a) {
+    const uint32_t b = a >> 5, o = a & 31;
+    const uint4 x = blk[b], y = blk[b + 1];
+    const uint64_t c0 = (uint64_t(x.x) << 32) | x.y, c1 = (uint64_t(y.x) << 32) | y.y;
+    Window w;
+    w.code = o ? (c0 << (2 * o)) | (c1 >> (64 - 2 * o)) : c0;
+    w.sep = o ? (x.z << o) | (y.z >> (32 - o)) : x.z;
+    return w;
 }
 
 template <int CH>
-__global__ __launch_bounds__(256) void k_kasai(const uint32_t *__restrict__ packed,
-                                               const uint32_t *__restrict__ sepmask,
+__global__ __launch_bounds__(256) void k_kasai(const uint4 *__restrict__ blk,
                                                const int32_t *__restrict__ sa,
                                                const int32_t *__restrict__ isa,
                                                int32_t *__restrict__ lcp, uint32_t n,
@@ -72,8 +82,9 @@ __global__ __launch_bounds__(256) void k_kasai(const uint32_t *__restrict__ pack
                 raise_err(err, kErrRange);
                 break;
             }
-            const uint64_t d = window64(packed, p + h) ^ window64(packed, q + h);
-            const uint32_t sp = sepwin32(sepmask, p + h) | sepwin32(sepmask, q + h);
+            const Window a = window_at(blk, p + h), b = window_at(blk, q + h);
+            const uint64_t d = a.code ^ b.code;
+            const uint32_t sp = a.sep | b.sep;
             const uint32_t md = d ? uint32_t(__clzll((long long)d)) >> 1 : 32u;
             const uint32_t ms = sp ? uint32_t(__clz(sp)) : 32u;
             const uint32_t kk = md < ms ? md : ms;
@@ -97,6 +108,7 @@ extern "C" int64_t sa_lcp_ws_bytes(int64_t n) {
     c.take<uint32_t>(packed_words(n));
     c.take<uint32_t>(sepmask_words(n));
     c.take<uint32_t>(sepmask_words(n));
+    c.take<uint4>(sepmask_words(n));
     c.take<uint32_t>(64);
     return c.off + 256;
 }
@@ -111,20 +123,24 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
     uint32_t *packed = c.take<uint32_t>(packed_words(n));
     uint32_t *sepmask = c.take<uint32_t>(sepmask_words(n));
     uint32_t *wordcnt = c.take<uint32_t>(sepmask_words(n));
+    uint4 *blk = c.take<uint4>(sepmask_words(n));
     uint32_t *err = c.take<uint32_t>(64);
     SA_TRY(launch_fill_u32(err, 1, 0, stream));
     SA_TRY(launch_pack(text, n, packed, sepmask, wordcnt, err, stream));
+    const int64_t nrec = sepmask_words(n);
+    hipLaunchKernelGGL(k_blocks, dim3(unsigned((nrec + 255) / 256)), dim3(256), 0, stream, packed,
+                       sepmask, blk, nrec);
     const uint32_t chunk = g_lcp_chunk;
     const int64_t threads = (n + chunk - 1) / chunk;
     const dim3 grid(unsigned((threads + 255) / 256)), block(256);
     // algorithmic bytes: isa[p] (4) + sa[isa[p]-1] (4) + lcp write (4) per position
     TimedScope ts("kasai", double(n) * 12.0, stream);
     switch (chunk) {
-        case 1: hipLaunchKernelGGL(k_kasai<1>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
-        case 2: hipLaunchKernelGGL(k_kasai<2>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
-        case 4: hipLaunchKernelGGL(k_kasai<4>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
-        case 8: hipLaunchKernelGGL(k_kasai<8>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
-        default: hipLaunchKernelGGL(k_kasai<16>, grid, block, 0, stream, packed, sepmask, sa, isa, lcp, uint32_t(n), err); break;
+        case 1: hipLaunchKernelGGL(k_kasai<1>, grid, block, 0, stream, blk, sa, isa, lcp, uint32_t(n), err); break;
+        case 2: hipLaunchKernelGGL(k_kasai<2>, grid, block, 0, stream, blk, sa, isa, lcp, uint32_t(n), err); break;
+        case 4: hipLaunchKernelGGL(k_kasai<4>, grid, block, 0, stream, blk, sa, isa, lcp, uint32_t(n), err); break;
+        case 8: hipLaunchKernelGGL(k_kasai<8>, grid, block, 0, stream, blk, sa, isa, lcp, uint32_t(n), err); break;
+        default: hipLaunchKernelGGL(k_kasai<16>, grid, block, 0, stream, blk, sa, isa, lcp, uint32_t(n), err); break;
     }
     ts.finish();
     SA_HIP(hipGetLastError());

@@ -9,7 +9,7 @@
 //
 // Here one pass is one kernel per tile of keys ("onesweep"):
 //   * the digit counts of every pass are taken once, up front (k_hist or the key builders),
-//     and scanned per pass into global digit bases (k_hist_scan);
+//     and summed and scanned per pass into global digit bases (k_hist_sum, k_hist_bases);
 //   * each workgroup ranks its tile by digit with wave64 ballots (a d-bit multisplit instead
 //     of d one-bit splits), publishes its per-digit counts in a (tile x digit) table and
 //     reads the prefix of earlier tiles from that table by decoupled look-back -- the prefix
@@ -94,46 +94,55 @@ __global__ __launch_bounds__(256) void k_hist(const uint64_t *__restrict__ keys,
     hist_flush<D>(s_h, hist, passes);
 }
 
-// Sum the partial histograms of one pass and scan them into exclusive digit bases (one
-// 1024-thread workgroup per pass; every digit's partials are split over several threads).
+// Digit totals of every pass from the per-workgroup partial histograms: workgroup (pass,
+// g) sums digits 64g .. 64g+63 with 16 threads per digit, each over every 16th partial.
 constexpr int kHsBlock = 1024;
+constexpr int kHsDigits = 64;
+constexpr int kHsSlices = kHsBlock / kHsDigits;
 template <int D>
-__global__ __launch_bounds__(kHsBlock) void k_hist_scan(const uint32_t *__restrict__ part,
-                                                        int nparts, int passes,
-                                                        uint32_t *__restrict__ gbase) {
+__global__ __launch_bounds__(kHsBlock) void k_hist_sum(const uint32_t *__restrict__ part,
+                                                       int nparts, int passes,
+                                                       uint32_t *__restrict__ tot) {
     constexpr int R = 1 << D;
-    constexpr int T = R >= kHsBlock ? 1 : kHsBlock / R;  // threads per digit
-    constexpr int PER = (R + kHsBlock - 1) / kHsBlock;    // digits per thread in the scan
-    __shared__ uint32_t s_w[kHsBlock / kWave];
-    __shared__ uint32_t s_part[R * T];
-    const uint32_t *src = part + size_t(blockIdx.x) * R;
-    const size_t stride = size_t(passes) * R;
-    for (int idx = threadIdx.x; idx < R * T; idx += kHsBlock) {
-        const int d = idx % R, k = idx / R;
-        uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int w = k;
-        for (; w + 3 * T < nparts; w += 4 * T) {
-            a0 += src[size_t(w) * stride + d];
-            a1 += src[size_t(w + T) * stride + d];
-            a2 += src[size_t(w + 2 * T) * stride + d];
-            a3 += src[size_t(w + 3 * T) * stride + d];
+    __shared__ uint32_t s_part[kHsSlices][kHsDigits];
+    const int pass = blockIdx.x, dl = threadIdx.x % kHsDigits, sl = threadIdx.x / kHsDigits;
+    const int d = blockIdx.y * kHsDigits + dl;
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    if (d < R) {
+        const uint32_t *src = part + size_t(pass) * R + d;
+        const size_t stride = size_t(passes) * R;
+        int w = sl;
+        for (; w + 3 * kHsSlices < nparts; w += 4 * kHsSlices) {
+            a0 += src[size_t(w) * stride];
+            a1 += src[size_t(w + kHsSlices) * stride];
+            a2 += src[size_t(w + 2 * kHsSlices) * stride];
+            a3 += src[size_t(w + 3 * kHsSlices) * stride];
         }
-        for (; w < nparts; w += T) a0 += src[size_t(w) * stride + d];
-        s_part[idx] = a0 + a1 + a2 + a3;
+        for (; w < nparts; w += kHsSlices) a0 += src[size_t(w) * stride];
     }
+    s_part[sl][dl] = a0 + a1 + a2 + a3;
     __syncthreads();
-    uint32_t *g = gbase + blockIdx.x * R;
+    if (sl == 0 && d < R) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kHsSlices; ++k) c += s_part[k][dl];
+        tot[size_t(pass) * R + d] = c;
+    }
+}
+
+// Exclusive scan of one pass's digit totals into digit bases, in place (one workgroup per pass).
+template <int D>
+__global__ __launch_bounds__(kHsBlock) void k_hist_bases(uint32_t *__restrict__ gbase) {
+    constexpr int R = 1 << D;
+    constexpr int PER = (R + kHsBlock - 1) / kHsBlock;  // digits per thread
+    __shared__ uint32_t s_w[kHsBlock / kWave];
+    uint32_t *g = gbase + size_t(blockIdx.x) * R;
     uint32_t v[PER], sum = 0;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int d = threadIdx.x * PER + j;
-        uint32_t c = 0;
-        if (d < R) {
-#pragma unroll
-            for (int k = 0; k < T; ++k) c += s_part[k * R + d];
-        }
-        v[j] = c;
-        sum += c;
+        v[j] = d < R ? g[d] : 0u;
+        sum += v[j];
     }
     uint32_t total;
     uint32_t run = block_excl_sum<kHsBlock>(sum, s_w, &total);
@@ -143,6 +152,15 @@ __global__ __launch_bounds__(kHsBlock) void k_hist_scan(const uint32_t *__restri
         if (d < R) g[d] = run;
         run += v[j];
     }
+}
+
+template <int D>
+static void launch_hist_scan(const uint32_t *hist, int nparts, int P, uint32_t *gbase,
+                             hipStream_t s) {
+    constexpr int R = 1 << D;
+    hipLaunchKernelGGL(k_hist_sum<D>, dim3(unsigned(P), unsigned((R + kHsDigits - 1) / kHsDigits)),
+                       dim3(kHsBlock), 0, s, hist, nparts, P, gbase);
+    hipLaunchKernelGGL(k_hist_bases<D>, dim3(unsigned(P)), dim3(kHsBlock), 0, s, gbase);
 }
 
 static unsigned hist_grid(int64_t n) {
@@ -213,11 +231,22 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
         uint64_t key[ITEMS];
         uint32_t val[ITEMS];
         uint32_t pos[ITEMS];
+        const bool full = tbase + uint32_t(TILE) <= n;
+        if (full) {  // one base address per wave and immediate offsets per item
+            const uint64_t *kp = kin + (wbase + lane);
+            const uint32_t *vp = vin + (wbase + lane);
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t idx = wbase + k * kWave + lane;
-            key[k] = idx < n ? kin[idx] : 0;
-            val[k] = idx < n ? vin[idx] : 0;
+            for (int k = 0; k < ITEMS; ++k) {
+                key[k] = kp[k * kWave];
+                val[k] = vp[k * kWave];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * kWave + lane;
+                key[k] = idx < n ? kin[idx] : 0;
+                val[k] = idx < n ? vin[idx] : 0;
+            }
         }
 
         // Stable rank of every item among the items of its wave with the same digit: items
@@ -227,13 +256,16 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
             const uint32_t idx = wbase + k * kWave + lane;
             const bool valid = idx < n;
             const uint32_t dg = valid ? (uint32_t(key[k] >> shift) & dmask) : 0u;
-            uint64_t m = ballot(valid);
+            const uint64_t vm = ballot(valid);
+            uint32_t mlo = uint32_t(vm), mhi = uint32_t(vm >> 32);
 #pragma unroll
             for (int b = 0; b < D; ++b) {
-                const bool bit = (dg >> b) & 1u;
-                const uint64_t bb = ballot(bit);
-                m &= bit ? bb : ~bb;
+                const uint32_t sb = uint32_t(int32_t(dg << (31 - b)) >> 31);
+                const uint64_t bb = ballot(sb != 0);
+                mlo &= ~(uint32_t(bb) ^ sb);
+                mhi &= ~(uint32_t(bb >> 32) ^ sb);
             }
+            const uint64_t m = (uint64_t(mhi) << 32) | mlo;
             if (valid) {
                 const uint64_t lt = m & lanemask_lt();
                 const uint32_t c0 = s_wcnt[wave * R + dg];
@@ -384,10 +416,10 @@ int sort_run(const SortBufs &b, int cur, const uint32_t *count_dev, int64_t n, i
     if (P == 0 || n <= 1) return SA_OK;
     const int R = t.radix();
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_hist_scan<4>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
-        case 8: hipLaunchKernelGGL(k_hist_scan<8>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
-        case 9: hipLaunchKernelGGL(k_hist_scan<9>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
-        case 11: hipLaunchKernelGGL(k_hist_scan<11>, dim3(P), dim3(kHsBlock), 0, s, b.hist, nparts, P, b.gbase); break;
+        case 4: launch_hist_scan<4>(b.hist, nparts, P, b.gbase, s); break;
+        case 8: launch_hist_scan<8>(b.hist, nparts, P, b.gbase, s); break;
+        case 9: launch_hist_scan<9>(b.hist, nparts, P, b.gbase, s); break;
+        case 11: launch_hist_scan<11>(b.hist, nparts, P, b.gbase, s); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     SA_HIP(hipGetLastError());

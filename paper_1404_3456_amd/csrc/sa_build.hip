@@ -51,11 +51,15 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     uint32_t n, int round0, uint32_t h0, int rbits, int32_t *__restrict__ sa,
     uint32_t *__restrict__ rank, uint32_t *__restrict__ S_new, uint64_t *lbflags, uint32_t *tick,
     uint32_t *state, uint32_t *err) {
-    __shared__ uint64_t s_k[kRuTile + 2];
-    __shared__ uint32_t s_s[kRuTile];
+    // Global memory is only touched in wave-contiguous (striped) order; the per-item logic
+    // works on blocked runs of kRuItems consecutive items held in LDS.
+    __shared__ uint64_t s_k[kRuTile + 2];  // keys, one neighbour each side; then the outputs
+    __shared__ uint32_t s_s[kRuTile];      // suffix-array slots
+    __shared__ uint32_t s_v[kRuTile];      // text positions
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_w[kRuBlock / kWave];
     __shared__ uint64_t s_excl;
+    constexpr uint32_t kNone = 0xffffffffu;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t A = state[kStActive];
     const uint32_t ntiles = (A + kRuTile - 1) / kRuTile;
@@ -64,23 +68,17 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
     const uint32_t tbase = tile * kRuTile;
-    // keys and slots of the tile (coalesced), one key of neighbour on each side
     for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock) {
         const bool in = tbase + i < A;
         s_k[1 + i] = in ? K[tbase + i] : 0;
         s_s[i] = in ? (S ? S[tbase + i] : tbase + i) : 0;
+        s_v[i] = in ? V[tbase + i] : 0;
     }
     if (tid == 0) s_k[0] = tbase > 0 ? K[tbase - 1] : 0;
     if (tid == 1) s_k[kRuTile + 1] = (tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
-    const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
-    uint32_t v[kRuItems];
-#pragma unroll
-    for (int j = 0; j < kRuItems; ++j) {
-        const uint32_t i = tbase + first + j;
-        v[j] = i < A ? V[i] : 0;  // issued before the scan and look-back
-    }
     __syncthreads();
 
+    const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
     bool head[kRuItems + 1];
 #pragma unroll
     for (int j = 0; j <= kRuItems; ++j) {
@@ -126,25 +124,45 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     uint32_t out = uint32_t(state_in >> 31);
     uint32_t g1 = uint32_t(state_in & CountLastOp::kLastMask);  // last head index + 1
     const uint64_t lmask = (uint64_t(1) << rbits) - 1;
+    uint32_t lab_w[kRuItems], out_w[kRuItems];  // rank word and next-round index, or kNone
 #pragma unroll
     for (int j = 0; j < kRuItems; ++j) {
         const uint32_t li = first + j;
         const uint32_t i = tbase + li;
+        lab_w[j] = kNone;
+        out_w[j] = kNone;
         if (i < A) {
             if (head[j]) g1 = i + 1;
             const bool single = head[j] && head[j + 1];
             const uint32_t g = g1 - 1;  // i == 0 is always a head, so g1 >= 1
-            const uint32_t slot = s_s[li];
             const uint32_t label = g >= tbase ? s_s[g - tbase] : (S ? S[g] : g);
-            if (slot >= n || v[j] >= n || label >= n) {  // inconsistent input: report only
+            if (s_s[li] >= n || s_v[li] >= n || label >= n) {  // inconsistent input: report only
                 raise_err(err, kErrRange);
                 continue;
             }
-            sa[slot] = int32_t(v[j]);
             const bool same = !round0 && uint32_t((s_k[1 + li] >> rbits) & lmask) == label;
-            if (single || !same) rank[v[j]] = label | (single ? kDone : 0u);
-            if (!single) S_new[out++] = slot;
+            if (single || !same) lab_w[j] = label | (single ? kDone : 0u);
+            if (!single) out_w[j] = out++;
         }
+    }
+    __syncthreads();  // every read of the keys is done: their storage now holds the outputs
+    uint32_t *s_lab = reinterpret_cast<uint32_t *>(s_k);
+    uint32_t *s_out = s_lab + kRuTile;
+#pragma unroll
+    for (int j = 0; j < kRuItems; ++j) {
+        s_lab[first + j] = lab_w[j];
+        s_out[first + j] = out_w[j];
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock) {
+        if (tbase + i >= A) break;
+        const uint32_t slot = s_s[i], v = s_v[i];
+        if (slot >= n || v >= n) continue;  // reported above
+        sa[slot] = int32_t(v);
+        const uint32_t lw = s_lab[i];
+        if (lw != kNone) rank[v] = lw;
+        const uint32_t o = s_out[i];
+        if (o != kNone) S_new[o] = slot;
     }
 }
 
