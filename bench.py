@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--workers", type=int, default=3, help="serving: server worker streams")
     ap.add_argument("--max-jobs", type=int, default=64, help="serving: jobs per batch at most")
     ap.add_argument("--p99-bound-ms", type=float, default=500.0, help="serving: p99 bound")
+    ap.add_argument("--patterns", type=int, default=1_000_000, help="lookup: patterns per step")
+    ap.add_argument("--pattern-len", type=int, default=40, help="lookup: pattern length")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "radix_pass_traffic.json"),
                     help="JSON with HBM bytes per radix-pass launch from rocprofv3 counters")
     return ap.parse_args()
@@ -267,6 +269,59 @@ def bench_serving(args, pkg, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_lookup(args, pkg, torch, np):
+    """Pattern lookup over the plain large workload's suffix array: one step = sa_lookup of
+    `--patterns` seeded patterns of `--pattern-len` bases (substrings, read prefixes and random
+    strings), patterns and suffix array resident in HBM."""
+    from paper_1404_3456_amd import synth
+    r = synth.large_plain()
+    dev = torch.device("cuda:0")
+    text = torch.from_numpy(r.text).to(dev)
+    sa, _ = pkg.sa_build(text)
+    L = args.pattern_len
+    pats = synth.lookup_patterns(r.text, args.patterns, 0, L, L)
+    off_h = np.zeros(len(pats) + 1, dtype=np.int64)
+    off_h[1:] = np.cumsum([len(p) for p in pats])
+    buf = torch.from_numpy(np.frombuffer(b"".join(pats), dtype=np.uint8).copy()).to(dev)
+    off = torch.from_numpy(off_h).to(dev)
+    log(f"lookup: n={r.n}, {len(pats)} patterns, {int(off_h[-1])} bases")
+    for _ in range(args.warmup):
+        pkg.sa_lookup(text, sa, (buf, off))
+    torch.cuda.synchronize()
+    pkg.sa_timing_reset()
+    pkg.sa_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = pkg.sa_lookup(text, sa, (buf, off))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pkg.sa_timing_enable(False)
+    ms = (t1 - t0) * 1000.0 / args.steps
+    Lk, kms, _ = pkg.sa_timing_get("lookup")
+    res = res.cpu().numpy()
+    found = int((res[:, 1] > res[:, 0]).sum())
+    # modelled bytes per lookup: two binary searches of ceil(log2 n) steps, each touching one
+    # 64-byte line of the suffix array and one of the text records (an upper bound: the first
+    # levels are shared by all patterns and stay cached)
+    steps = 2 * int(np.ceil(np.log2(r.n)))
+    model = len(pats) * steps * 128.0
+    kern_s = kms * 1e-3 / Lk
+    print(json.dumps({
+        "metric": "pattern lookups per second (SA interval of each pattern)",
+        "value": round(len(pats) / (ms * 1e-3) / 1e6, 3), "unit": "Mlookups/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "lookup-plain-large-5M", "n_suffixes": r.n, "patterns": len(pats),
+                   "pattern_len": L, "found": found},
+        "kernel_ms": round(kern_s * 1e3, 4),
+        "roofline": {"bound": "hbm", "achieved": round(model / kern_s / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(model / kern_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_lookup", "model": "2*ceil(log2 n) steps x 128 B per lookup"},
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +339,8 @@ def main():
         return bench_batched(args, pkg, torch, np)
     if args.workload == "serving":
         return bench_serving(args, pkg, torch, np)
+    if args.workload == "lookup":
+        return bench_lookup(args, pkg, torch, np)
     if args.workload == "plain-large-5M":
         r = synth.large_plain()
     elif args.workload == "repeat-stress-40M":

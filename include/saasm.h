@@ -11,8 +11,8 @@
  *    library never allocates device memory inside these calls and never frees caller memory.
  *    Workspace contents are scratch: nothing is carried from one call to the next.
  *  - Streams: every call is ordered on `stream`.  Calls that report a count or status to the
- *    host (sa_build, sa_overlaps, sa_pack, sa_sort_pairs) synchronise `stream` before they
- *    return; sa_lcp does not.
+ *    host (sa_build, sa_overlaps, sa_lookup, sa_pack, sa_sort_pairs) synchronise `stream`
+ *    before they return; sa_lcp does not.
  *  - Errors: every call returns an int status (SA_OK or a negative SA_ERR_*) and never throws
  *    across the ABI.  sa_last_error() returns a message for the calling thread's last failure.
  *    On error the outputs are unspecified; inputs are never modified.
@@ -165,6 +165,30 @@ int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa
  * carried bound at its first position; any value gives the same result).  Process-wide;
  * default 4. */
 int sa_lcp_set_chunk(int32_t chunk);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Pattern lookup (Sec. IV: the suffix array is searched to decide whether a string -- e.g. a  */
+/* fragment -- is a prefix of a suffix of the text).                                          */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for sa_lookup on a text of n bytes with patterns of pat_total bytes in all. */
+int64_t sa_lookup_ws_bytes(int64_t n, int64_t pat_total);
+
+/* sa_lookup: for each pattern P_i = pat[pat_off[i] .. pat_off[i+1]) over A, C, G, T, the
+ * interval [lo, hi) of suffix-array indices whose suffixes start with P_i:
+ *   lohi[2i] = lo  = number of suffixes that sort below P_i without starting with it,
+ *   lohi[2i+1] = hi, so hi - lo = number of positions where P_i occurs in the text.
+ * An empty pattern gives [0, n).  Patterns never match across a separator.
+ *   text     [n] the text sa was built from
+ *   sa       [n] from sa_build on that text
+ *   pat      [pat_total] pattern bytes, concatenated (may be NULL when pat_total == 0)
+ *   pat_off  [n_pat + 1] int64, non-decreasing, pat_off[0] >= 0, pat_off[n_pat] <= pat_total
+ *   lohi     [2 * n_pat] int32 out
+ * Errors: SA_ERR_ALPHABET when a pattern (or the text) holds another byte; SA_ERR_INVALID for
+ * offsets out of range or a text without its final '$'.  Synchronises the stream. */
+int sa_lookup(const uint8_t *text, int64_t n, const int32_t *sa, const uint8_t *pat,
+              const int64_t *pat_off, int64_t pat_total, int32_t n_pat, int32_t *lohi,
+              void *ws, int64_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Suffix-prefix overlaps between fragments (Sec. III: a fragment is 'fir' when it is a prefix */

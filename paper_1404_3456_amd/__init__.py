@@ -30,6 +30,8 @@ from ._abi import (  # noqa: F401
     sa_lcp,
     sa_lcp_set_chunk,
     sa_lcp_ws_bytes,
+    sa_lookup,
+    sa_lookup_ws_bytes,
     sa_overlaps,
     sa_overlaps_ws_bytes,
     sa_pack,

@@ -79,6 +79,8 @@ def load():
         "sa_build_batched_ws_bytes": ([I64, I32, P, TP], I64),
         "sa_build_batched": ([P, I64, P, I32, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
         "sa_lcp_ws_bytes": ([I64], I64),
+        "sa_lookup_ws_bytes": ([I64, I64], I64),
+        "sa_lookup": ([P, I64, P, P, P, I64, ctypes.c_int32, P, P, I64, P], ctypes.c_int),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
         "sa_lcp_set_chunk": ([I32], ctypes.c_int),
         "sa_overlaps_ws_bytes": ([I64, I64, I64], I64),
@@ -274,6 +276,37 @@ def sa_lcp(text, sa, isa, stream=None):
     _check(lib.sa_lcp(_ptr(t), n, _ptr(sa), _ptr(isa), _ptr(lcp), _ptr(ws), ws.numel(),
                       _stream(stream)))
     return lcp
+
+
+def sa_lookup_ws_bytes(n: int, pat_total: int) -> int:
+    return int(load().sa_lookup_ws_bytes(n, pat_total))
+
+
+def sa_lookup(text, sa, patterns, stream=None):
+    """SA interval [lo, hi) of the suffixes that start with each pattern: (k, 2) int32 device
+    tensor.  `patterns` is a list of byte strings, or a pair (device uint8 tensor of the
+    concatenated patterns, device int64 tensor of k+1 offsets)."""
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    if isinstance(patterns, tuple):
+        buf, off = patterns
+    else:
+        import numpy as np
+        pats = [bytes(p) for p in patterns]
+        off_h = np.zeros(len(pats) + 1, dtype=np.int64)
+        off_h[1:] = np.cumsum([len(p) for p in pats])
+        raw = np.frombuffer(b"".join(pats) or b"\0", dtype=np.uint8).copy()
+        buf = torch.from_numpy(raw).to(t.device)
+        off = torch.from_numpy(off_h).to(t.device)
+    k = off.numel() - 1
+    total = int(buf.numel())
+    out = torch.empty((max(k, 0), 2), dtype=torch.int32, device=t.device)
+    ws = _ws(sa_lookup_ws_bytes(n, total), t.device)
+    _check(lib.sa_lookup(_ptr(t), n, _ptr(sa), _ptr(buf), _ptr(off), total, k, _ptr(out),
+                         _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 def sa_lcp_set_chunk(chunk: int):

@@ -87,6 +87,9 @@ int64_t sepmask_words(int64_t n);
 // pack: packed/sepmask/per-word separator counts; err bits OR-ed into *err.
 int launch_pack(const uint8_t *text, int64_t n, uint32_t *packed, uint32_t *sepmask,
                 uint32_t *wordcnt, uint32_t *err, hipStream_t s);
+// block layout for random-access windows (text.hpp): nrec = sepmask_words(n) records
+int launch_blocks(const uint32_t *packed, const uint32_t *sepmask, uint4 *blk, int64_t nrec,
+                  hipStream_t s);
 // exclusive scan of uint32 values into int32 (out[i] = sum of in[0..i)); total -> *total_out
 int64_t scan_flags_words(int64_t n);
 int launch_scan_u32_i32(const uint32_t *in, int32_t *out, int64_t n, int32_t *total_out,

@@ -10,35 +10,9 @@
 // a separator in either suffix ends the match (two separators are different symbols).
 #include "device.hpp"
 #include "internal.hpp"
+#include "text.hpp"
 
 namespace saasm {
-
-// Text blocks for random-access windows: record b holds the packed codes of positions
-// 32b .. 32b+31 (two words, position 32b in the top bits of the first) and their separator
-// bits (position 32b in bit 31), padded to 16 bytes, so a 32-position window starting anywhere
-// is two aligned 16-byte loads instead of five scattered word loads.
-__global__ __launch_bounds__(256) void k_blocks(const uint32_t *__restrict__ packed,
-                                                const uint32_t *__restrict__ sepmask,
-                                                uint4 *__restrict__ blk, int64_t nrec) {
-    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= nrec) return;
-    blk[b] = make_uint4(packed[2 * b], packed[2 * b + 1], sepmask[b], 0u);
-}
-
-struct Window {
-    uint64_t code;  // 32 bases from position a, base a in bits 63..62
-    uint32_t sep;   // separator bits of positions a .. a+31, position a in bit 31
-};
-
-__device__ __forceinline__ Window window_at(const uint4 *__restrict__ blk, uint32_t a) {
-    const uint32_t b = a >> 5, o = a & 31;
-    const uint4 x = blk[b], y = blk[b + 1];
-    const uint64_t c0 = (uint64_t(x.x) << 32) | x.y, c1 = (uint64_t(y.x) << 32) | y.y;
-    Window w;
-    w.code = o ? (c0 << (2 * o)) | (c1 >> (64 - 2 * o)) : c0;
-    w.sep = o ? (x.z << o) | (y.z >> (32 - o)) : x.z;
-    return w;
-}
 
 template <int CH>
 __global__ __launch_bounds__(256) void k_kasai(const uint4 *__restrict__ blk,
@@ -127,9 +101,7 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
     uint32_t *err = c.take<uint32_t>(64);
     SA_TRY(launch_fill_u32(err, 1, 0, stream));
     SA_TRY(launch_pack(text, n, packed, sepmask, wordcnt, err, stream));
-    const int64_t nrec = sepmask_words(n);
-    hipLaunchKernelGGL(k_blocks, dim3(unsigned((nrec + 255) / 256)), dim3(256), 0, stream, packed,
-                       sepmask, blk, nrec);
+    SA_TRY(launch_blocks(packed, sepmask, blk, sepmask_words(n), stream));
     const uint32_t chunk = g_lcp_chunk;
     const int64_t threads = (n + chunk - 1) / chunk;
     const dim3 grid(unsigned((threads + 255) / 256)), block(256);

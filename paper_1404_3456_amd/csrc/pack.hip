@@ -72,6 +72,24 @@ int launch_pack(const uint8_t *text, int64_t n, uint32_t *packed, uint32_t *sepm
     return SA_OK;
 }
 
+// Block layout of the text for random-access windows (see text.hpp): record b = {codes of
+// positions 32b..32b+15, codes of 32b+16..32b+31, separator bits of 32b..32b+31, 0}.
+__global__ __launch_bounds__(256) void k_blocks(const uint32_t *__restrict__ packed,
+                                                const uint32_t *__restrict__ sepmask,
+                                                uint4 *__restrict__ blk, int64_t nrec) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nrec) return;
+    blk[b] = make_uint4(packed[2 * b], packed[2 * b + 1], sepmask[b], 0u);
+}
+
+int launch_blocks(const uint32_t *packed, const uint32_t *sepmask, uint4 *blk, int64_t nrec,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_blocks, dim3(unsigned((nrec + 255) / 256)), dim3(256), 0, s, packed,
+                       sepmask, blk, nrec);
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
 // ---- exclusive scan with decoupled look-back ------------------------------------------------
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;

@@ -271,3 +271,29 @@ WORKLOADS = {
     "plain-large-5M": large_plain,
     "repeat-stress-40M": repeat_stress,
 }
+
+
+def lookup_patterns(text: np.ndarray, count: int, seed: int, len_lo: int = 0,
+                    len_hi: int = 80) -> list:
+    """Seeded query strings for pattern lookup on ``text``: half are substrings of the text
+    (cut before the first separator they would cross), a quarter are read prefixes and a
+    quarter are uniform random A/C/G/T strings (mostly absent).  Lengths uniform in
+    [len_lo, len_hi]."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, 11, seed])))
+    tb = bytes(np.asarray(text, dtype=np.uint8))
+    starts = [0] + [i + 1 for i, c in enumerate(tb[:-1]) if c == ord("$")]
+    out = []
+    for j in range(count):
+        L = int(rng.integers(len_lo, len_hi + 1))
+        kind = j % 4
+        if kind in (0, 1):
+            p = int(rng.integers(0, len(tb)))
+        elif kind == 2:
+            p = starts[int(rng.integers(0, len(starts)))]
+        else:
+            out.append(bytes(rng.choice(list(b"ACGT"), size=L).astype(np.uint8)))
+            continue
+        s = tb[p:p + L]
+        cut = s.find(b"$")
+        out.append(s if cut < 0 else s[:cut])
+    return out

@@ -49,3 +49,15 @@ def test_full_plain_large(pkg):
 def test_full_repeat_stress(pkg):
     rows = full_check(pkg, synth.repeat_stress(), samples=200_000)
     assert rows > 0
+
+
+def test_full_lookup_plain_large(pkg):
+    """Pattern lookup on the 50.1 M-character suffix array: sampled patterns against the
+    oracle's definition over text positions."""
+    r = synth.large_plain()
+    print(f"full-size lookup {r.name}: n={r.n}", flush=True)
+    t = torch.from_numpy(r.text).cuda()
+    sa, _ = pkg.sa_build(t)
+    pats = synth.lookup_patterns(r.text, 48, 3, 20, 120)
+    got = pkg.sa_lookup(t, sa, pats).cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, oracle.lookup(r.text, pats))

@@ -296,3 +296,57 @@ def test_autotune_picks_a_valid_tuning(lib, tmp_path):
     assert rep2["cached"] is True and tu2 == tu
     sa, _ = lib.sa_build(t, tuning=tu)
     assert np.array_equal(sa.cpu().numpy(), oracle.suffix_array(t.cpu().numpy()))
+
+
+# ---- pattern lookup ------------------------------------------------------------------------
+
+def run_lookup(lib, text, patterns):
+    t = dev(text)
+    sa, _ = lib.sa_build(t)
+    got = lib.sa_lookup(t, sa, patterns)
+    torch.cuda.synchronize()
+    return got.cpu().numpy().astype(np.int64)
+
+
+def test_lookup_small_workload(lib):
+    r = synth.small_plain()
+    pats = synth.lookup_patterns(r.text, 2000, 0, 0, 80)
+    assert np.array_equal(run_lookup(lib, r.text, pats), oracle.lookup(r.text, pats))
+
+
+def test_lookup_long_and_edge_patterns(lib):
+    """Patterns across several 32-base windows, whole reads, reads plus one base, patterns
+    longer than any read, the empty pattern, and texts with empty reads."""
+    text = synth.genome_reads(5, 3000, 120, 150, err=0.002)
+    tb = bytes(text)
+    reads = [x for x in tb.split(b"$")[:-1]]
+    pats = [b"", b"A", b"T" * 40] + reads[:20] + [x + b"A" for x in reads[:10]]
+    pats += [tb[p:p + L].split(b"$")[0] for p in range(0, 2000, 37) for L in (31, 32, 33, 64, 65, 149)]
+    pats += [reads[0] * 2, b"ACGT" * 50]
+    assert np.array_equal(run_lookup(lib, text, pats), oracle.lookup(text, pats))
+    p2 = [b"", b"A", b"AA", b"C", b"A" * 36, b"A" * 2999, b"A" * 3001, b"ACG" * 40, b"GATTACA",
+          b"ACGTACGT", b"T"]
+    for name in sorted(EDGE):
+        t = np.frombuffer(EDGE[name], dtype=np.uint8).copy()
+        assert np.array_equal(run_lookup(lib, t, p2), oracle.lookup(t, p2)), name
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_lookup_ragged_random(lib, seed):
+    text = synth.random_dna_reads(40 + seed, 500, 0, 90, allow_empty=True)
+    pats = synth.lookup_patterns(text, 1500, seed + 1, 0, 40)
+    assert np.array_equal(run_lookup(lib, text, pats), oracle.lookup(text, pats))
+
+
+def test_lookup_rejects_bad_patterns(lib):
+    text = synth.random_dna_reads(3, 20, 5, 30)
+    t = dev(text)
+    sa, _ = lib.sa_build(t)
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_lookup(t, sa, [b"ACGT", b"ACNT"])
+    assert e.value.code == lib.SA_ERR_ALPHABET
+    buf = dev(np.frombuffer(b"ACGTACGT", dtype=np.uint8).copy())
+    off = dev(np.array([0, 5, 3], dtype=np.int64))  # decreasing offsets
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_lookup(t, sa, (buf, off))
+    assert e.value.code == lib.SA_ERR_INVALID

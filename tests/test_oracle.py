@@ -230,6 +230,73 @@ def test_rejects_bad_text():
         oracle.suffix_array(b"")
 
 
+# ---- pattern lookup -------------------------------------------------------------------------
+
+LOOKUP_PATTERNS = [b""] + [bytes(x) for L in (1, 2, 3) for x in itertools.product(b"ACGT", repeat=L)]
+
+
+def _lookup_matches_brute(lookup_fn, t, patterns):
+    got = lookup_fn(t, patterns).tolist()
+    return got == [list(brute.lookup(t, p)) for p in patterns]
+
+
+def test_lookup_vs_brute_tiny():
+    """Every pattern of length <= 3 on a sample of the tiny texts, against the SA-based literal
+    definition of the interval."""
+    for t in TINY[::13]:
+        assert _lookup_matches_brute(oracle.lookup, t, LOOKUP_PATTERNS), t
+
+
+@pytest.mark.parametrize("k", [1, 3, 9])
+def test_lookup_homopolymer_closed_form(k):
+    """Text A^k$: the suffixes are $, A$, ..., A^k$ in that order, so A^j (1 <= j <= k) starts
+    exactly the last k-j+1 of them: [j, k+1); A^(k+1) starts none and sorts after all."""
+    t = b"A" * k + b"$"
+    pats = [b"A" * j for j in range(1, k + 2)] + [b"C", b""]
+    got = oracle.lookup(t, pats).tolist()
+    want = [[j, k + 1] for j in range(1, k + 1)] + [[k + 1, k + 1], [k + 1, k + 1], [0, k + 1]]
+    assert got == want
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lookup_interval_invariants(seed):
+    """On random reads: the interval width is the number of occurrences (counted with
+    str.find), every suffix inside starts with the pattern, and its neighbours do not."""
+    rng = np.random.default_rng(seed)
+    reads = ["".join(rng.choice(list("ACGT"), size=int(rng.integers(0, 30)))) for _ in range(40)]
+    t = synth.text_from_strings(reads)
+    sa = oracle.suffix_array(t)
+    tb = bytes(t)
+    pats = [tb[p:p + L] for p, L in zip(rng.integers(0, len(tb) - 8, 60), rng.integers(1, 8, 60))]
+    pats = [p for p in pats if b"$" not in p] + [b"ACGTACGTAC", b"TTTTT"]
+    for p, (lo, hi) in zip(pats, oracle.lookup(t, pats).tolist()):
+        occ, i = 0, tb.find(p)
+        while i >= 0:
+            occ, i = occ + 1, tb.find(p, i + 1)
+        assert hi - lo == occ
+        assert all(tb[q:q + len(p)] == p for q in sa[lo:hi])
+        if lo > 0:
+            assert tb[sa[lo - 1]:sa[lo - 1] + len(p)] != p
+        if hi < len(tb):
+            assert tb[sa[hi]:sa[hi] + len(p)] != p
+
+
+def test_lookup_worked_example_superstring():
+    """Sec. III worked example: the printed superstring contains every fragment, and merging
+    along the printed path places them in path order (first occurrences increase)."""
+    frags, path, superstring = _golden()
+    t = superstring.encode() + b"$"
+    res = oracle.lookup(t, [p.encode() for p in path]).tolist()
+    assert all(hi - lo >= 1 for lo, hi in res)
+    first = [superstring.find(p) for p in path]
+    assert first == sorted(first) and first[0] == 0
+
+
+def test_lookup_rejects_separator_in_pattern():
+    with pytest.raises(ValueError):
+        oracle.lookup(b"ACGT$", [b"A$"])
+
+
 # ---- planted mistakes: each mutant of the C oracle must fail some pin --------------------
 
 MUTANTS = {
@@ -247,6 +314,11 @@ MUTANTS = {
     # off by one at the minimum length
     "indexed_min_len_off_by_one": (r"for \(int64_t o = 0; o \+ min_len <= la; \+\+o\)",
                                    "for (int64_t o = 0; o + min_len < la; ++o)"),
+    # a suffix that ends at its separator counted above the pattern
+    "lookup_sep_above": (r"if \(x == SEPB\) return -1;  /\* the suffix ends first",
+                         "if (x == SEPB) return 1;  /* the suffix ends first"),
+    # suffixes that start with the pattern counted below it
+    "lookup_prefix_below": (r"if \(c < 0\) \+\+below;", "if (c <= 0) ++below;"),
 }
 
 
@@ -267,6 +339,9 @@ def _pins_pass(lib_dir):
                     return False
         if not check_worked_example(mod.overlaps) or not check_worked_example(mod.overlaps_brute):
             return False
+        for t in TINY[::97]:
+            if not _lookup_matches_brute(mod.lookup, t, LOOKUP_PATTERNS[:21]):
+                return False
         return True
     except Exception:
         return False
