@@ -42,14 +42,16 @@ def parse():
     ap.add_argument("--lcp-chunk", type=int, default=0)
     ap.add_argument("--max-total", type=int, default=0,
                     help="batched workload: stop adding sets once this many characters are drawn")
-    ap.add_argument("--no-graph", action="store_true", help="batched workload: no hipGraph replay")
+    ap.add_argument("--graph", action="store_true",
+                    help="batched workload: replay the doubling rounds from a hipGraph (default: "
+                         "host-driven rounds one ahead, measured faster)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose digit width, tile shape (and, batched, set packing) by measurement first")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run sa_copy_u32 over 256 MiB three times (counter calibration)")
     ap.add_argument("--pool", type=int, default=64, help="serving: distinct jobs generated")
     ap.add_argument("--jobs", type=int, default=300, help="serving: jobs per arrival-rate run")
-    ap.add_argument("--workers", type=int, default=3, help="serving: server worker streams")
+    ap.add_argument("--workers", type=int, default=4, help="serving: server worker streams")
     ap.add_argument("--max-jobs", type=int, default=64, help="serving: jobs per batch at most")
     ap.add_argument("--p99-bound-ms", type=float, default=500.0, help="serving: p99 bound")
     ap.add_argument("--patterns", type=int, default=1_000_000, help="lookup: patterns per step")
@@ -104,7 +106,7 @@ def bench_batched(args, pkg, torch, np):
         log(f"autotuned: {tuning}")
 
     def batched():
-        sa, isa = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=not args.no_graph)
+        sa, isa = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=args.graph)
         lcp = pkg.sa_lcp(text, sa, isa)
         ovl = pkg.sa_overlaps(text, sa, isa, lcp, min_len)
         return sa, ovl
@@ -148,7 +150,7 @@ def bench_batched(args, pkg, torch, np):
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": "batched-256: 256 sets, genome log-uniform 10 kbp-2 Mbp, reads "
                                "100-1000 bp, coverage 5-20x, 0.5% subs, overlaps >= 40",
-                   "sets": len(sets), "n_total": int(cat.size), "graph": not args.no_graph,
+                   "sets": len(sets), "n_total": int(cat.size), "graph": args.graph,
                    "tuning": tuning.__dict__ if tuning else "default"},
         "plain_jobs_per_s": round(len(sets) / tp, 3),
         "speedup_vs_plain": round(tp / tb, 3),
@@ -176,10 +178,11 @@ def bench_serving(args, pkg, torch, np):
     arena = 64 << 30
 
     def run(mode, rate, n_jobs, workers):
+        # the same job sequence for every run; only the arrival times depend on the rate
+        order = np.random.default_rng(1404).integers(0, pool_n, size=n_jobs)
         rng = np.random.default_rng(1404 + int(rate * 1000))
         gaps = rng.exponential(1.0 / rate, size=n_jobs) if rate > 0 else np.zeros(n_jobs)
         arr = np.cumsum(gaps) - gaps[0]
-        order = rng.integers(0, pool_n, size=n_jobs)
         lat = [None] * n_jobs
         pending = {}
         lock = threading.Lock()

@@ -51,7 +51,9 @@ enum {
 
 /* Launch tuning of the radix sort; a zero field means "use the default".
  *   digit_bits       4, 8, 9 or 11 bits per LSD pass
- *   block_threads    256 or 512 threads per workgroup (4 or 8 wave64 wavefronts; default 512)
+ *   block_threads    256, 512 or 1024 threads per workgroup (4, 8 or 16 wave64 wavefronts;
+ *                    1024 only with 16 items and digit_bits <= 9; default 1024, or 512 for
+ *                    11-bit digits)
  *   items_per_thread 8 or 16 keys per thread (tile = block_threads * items_per_thread)
  *   seg_pack         sa_build_batched only: at most this many characters per build
  *                    (consecutive texts are packed greedily; 0 = all texts in one build);

@@ -19,8 +19,8 @@ DEFAULT_CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser
                              "saasm", "autotune.json")
 
 # (digit_bits, block_threads, items_per_thread)
-TILE_CANDIDATES = [(8, 512, 16), (9, 512, 16), (8, 256, 16), (9, 256, 16), (8, 512, 8),
-                   (9, 512, 8), (11, 512, 16), (4, 512, 16)]
+TILE_CANDIDATES = [(8, 1024, 16), (9, 1024, 16), (8, 512, 16), (9, 512, 16), (8, 256, 16),
+                   (8, 512, 8), (11, 512, 16), (4, 1024, 16)]
 
 
 def _bucket(x: int) -> int:

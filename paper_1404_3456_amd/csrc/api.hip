@@ -25,11 +25,15 @@ int resolve_tuning(const sa_tuning *tu, Tune *out) {
         if (tu->block_threads) t.block = tu->block_threads;
         if (tu->items_per_thread) t.items = tu->items_per_thread;
         if (tu->seg_pack != 0) return fail(SA_ERR_INVALID, "seg_pack must be 0 for this call");
+        if (!tu->block_threads && t.dbits > 9) t.block = 512;  // the widest tile needs <= 9 bits
     }
     if (t.dbits != 4 && t.dbits != 8 && t.dbits != 9 && t.dbits != 11)
         return fail(SA_ERR_INVALID, "digit_bits must be 4, 8, 9 or 11");
-    if (t.block != 256 && t.block != 512) return fail(SA_ERR_INVALID, "block_threads must be 256 or 512");
+    if (t.block != 256 && t.block != 512 && t.block != 1024)
+        return fail(SA_ERR_INVALID, "block_threads must be 256, 512 or 1024");
     if (t.items != 8 && t.items != 16) return fail(SA_ERR_INVALID, "items_per_thread must be 8 or 16");
+    if (t.block == 1024 && (t.items != 16 || t.dbits > 9))
+        return fail(SA_ERR_INVALID, "block_threads 1024 needs items_per_thread 16 and digit_bits <= 9");
     *out = t;
     return SA_OK;
 }

@@ -50,7 +50,7 @@ struct Carver {
 // ---- tuning --------------------------------------------------------------------------------
 struct Tune {
     int dbits = 8;
-    int block = 512;
+    int block = 1024;  // 512 when digits are wider than 9 bits (resolve_tuning)
     int items = 16;
     int tile() const { return block * items; }
     int radix() const { return 1 << dbits; }
@@ -75,7 +75,7 @@ struct TimedScope {
     void finish();
 };
 int64_t timing_round_begin();                       // new tag for the calling thread's round
-void timing_round_items(int64_t tag, int64_t items);  // item count of that round (0: drop)
+void timing_round_items(int64_t tag, int64_t items);  // item count of that round (0: no bytes)
 void timing_flush();  // resolve pending events (waits for them)
 void timing_poll();   // resolve only the pending events that have already completed
 void timing_pause(bool on);  // calling thread: no events while a stream is being captured

@@ -406,6 +406,10 @@ static int launch_pass_d(const Tune &t, int64_t n_max, hipStream_t s, const uint
         return launch_pass_t<D, 512, 8>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
     if (t.block == 512 && t.items == 16)
         return launch_pass_t<D, 512, 16>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    if constexpr (D <= 9) {  // 1024 x 16: a 128 KB stage; with 11-bit digits the counters no longer fit
+        if (t.block == 1024 && t.items == 16)
+            return launch_pass_t<D, 1024, 16>(n_max, s, kin, vin, kout, vout, count_dev, n_host, shift, dmask, gbase, flags, tick, err);
+    }
     return fail(SA_ERR_INVALID, "unsupported tile shape");
 }
 

@@ -30,7 +30,7 @@
 
 namespace saasm {
 
-constexpr int kRuBlock = 256;
+constexpr int kRuBlock = 1024;
 constexpr int kRuItems = 8;
 constexpr int kRuTile = kRuBlock * kRuItems;
 
@@ -40,8 +40,10 @@ constexpr int kRuTile = kRuBlock * kRuItems;
 //               the suffix ended at its separator, which no other suffix shares);
 //   single(i) = head(i) and head(i+1) (i+1 == A counts as a head);
 //   label(i)  = S[g] where g is the last head at or before i.
-// Writes sa[S[i]] = V[i], rank[V[i]] = label | (single ? kDone : 0), and the slots of items
-// that are not singletons, compacted in order, to S_new; their count to state[kStNext].
+// Writes rank[V[i]] = label | (single ? kDone : 0), sa[S[i]] = V[i] once item i is a singleton
+// (its slot is then final; nothing reads the slots of suffixes still in a group), and the slots
+// of items that are not singletons, compacted in order, to S_new; their count to
+// state[kStNext].
 // In a doubling round the key's upper half is the item's previous label, so rank[V[i]] is
 // only rewritten when the label changes or the item becomes a singleton.
 // One tile per workgroup (tiles by ticket); the grid covers an upper bound on A and surplus
@@ -158,9 +160,11 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
         if (tbase + i >= A) break;
         const uint32_t slot = s_s[i], v = s_v[i];
         if (slot >= n || v >= n) continue;  // reported above
-        sa[slot] = int32_t(v);
         const uint32_t lw = s_lab[i];
-        if (lw != kNone) rank[v] = lw;
+        if (lw != kNone) {
+            rank[v] = lw;
+            if (lw & kDone) sa[slot] = int32_t(v);  // final; slots still in a group are rewritten later
+        }
         const uint32_t o = s_out[i];
         if (o != kNone) S_new[o] = slot;
     }

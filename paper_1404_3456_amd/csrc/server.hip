@@ -5,8 +5,9 @@
 // many such sets.  Jobs are submitted from any thread and queued.  Worker threads, each with its
 // own HIP stream, repeatedly take the queued jobs that fit (FIFO with bounded look-ahead, so a
 // large job at the head does not block small ones behind it for ever), lay their texts end to
-// end inside the arena, and run them as one batch: sa_build_batched (doubling rounds replayed
-// from a hipGraph), sa_lcp and sa_overlaps over the concatenation.  Results are localised per
+// end inside the arena, and run them as one batch: sa_build_batched (its doubling rounds driven
+// from the host one round ahead of the state it reads, so each batch costs no graph capture),
+// sa_lcp and sa_overlaps over the concatenation.  Results are localised per
 // job (positions, ranks and read ids relative to the job) and stay in the arena until the job
 // is released.  With several workers, a batch admitted while another is on the GPU runs
 // concurrently with it on another stream.
@@ -252,7 +253,7 @@ static int run_batch(asm_server *S, std::vector<Job *> &js, Batch *B, hipStream_
     if (S->mode == 1 && nj == 1)
         SA_TRY(sa_build(text, n, B->sa, B->isa, scr, scr_bytes, nullptr, &rounds, s));
     else
-        SA_TRY(sa_build_batched(text, n, off.data(), nj, B->sa, B->isa, scr, scr_bytes, nullptr, 1,
+        SA_TRY(sa_build_batched(text, n, off.data(), nj, B->sa, B->isa, scr, scr_bytes, nullptr, 0,
                                 &rounds, s));
     SA_TRY(sa_lcp(text, n, B->sa, B->isa, B->lcp, scr, scr_bytes, s));
     // overlaps (one min_len per batch; admission keeps it uniform), into scratch rows first

@@ -1,6 +1,8 @@
 """The C-ABI library loads and exports every symbol include/*.h declares; host-side argument
 checks run without a GPU (no compute call is made here)."""
 import ctypes
+
+import numpy as np
 import glob
 import os
 import re
@@ -74,6 +76,25 @@ def test_host_argument_checks_without_gpu():
     assert lib.sa_lcp(dummy, 100, dummy, None, dummy, dummy, 1 << 20, None) == _abi.SA_ERR_INVALID
     assert lib.sa_lcp_set_chunk(0) == _abi.SA_ERR_INVALID
     assert lib.sa_lcp_set_chunk(3) == _abi.SA_ERR_INVALID
+    # the 1024-thread tile needs 16 items and at most 9-bit digits
+    for tu in (_abi.Tuning(8, 1024, 8), _abi.Tuning(11, 1024, 16), _abi.Tuning(8, 768, 16)):
+        c = tu.c()
+        assert lib.sa_build(dummy, 100, dummy, None, dummy, 1 << 30, ctypes.byref(c), None,
+                            None) == _abi.SA_ERR_INVALID, tu
+    lk = np.zeros(2, dtype=np.int32)
+    assert lib.sa_lookup(None, 100, dummy, dummy, dummy, 4, 1, lk.ctypes.data_as(P), dummy,
+                         1 << 20, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_lookup(dummy, 100, dummy, dummy, dummy, 4, -1, lk.ctypes.data_as(P), dummy,
+                         1 << 20, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_lookup(dummy, 100, dummy, dummy, dummy, 4, 1, lk.ctypes.data_as(P), dummy,
+                         16, None) == _abi.SA_ERR_NOMEM
+
+
+def test_default_tile_for_wide_digits_is_accepted():
+    """11-bit digits with the tile left at its default resolve to a 512-thread tile (workspace
+    sizing goes through the same resolution, so a size comes back instead of an error)."""
+    assert _abi.sa_sort_ws_bytes(1000, _abi.Tuning(digit_bits=11)) > 0
+    assert _abi.sa_sort_ws_bytes(1000, _abi.Tuning(digit_bits=8)) > 0
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -88,6 +88,7 @@ def test_pack_rejects_bad_text(lib):
 # ---- radix sort: one pass is a stable counting sort; the whole sort is a stable sort ---------
 
 @pytest.mark.parametrize("tuning", [None, {"digit_bits": 4}, {"digit_bits": 9}, {"digit_bits": 11},
+                                    {"block_threads": 512, "items_per_thread": 16},
                                     {"block_threads": 512, "items_per_thread": 8},
                                     {"block_threads": 256, "items_per_thread": 8}])
 @pytest.mark.parametrize("bits", [(0, 64), (0, 8), (3, 14), (32, 49), (60, 64)])
@@ -194,7 +195,8 @@ def test_small_plain_workload(lib):
 
 
 TUNINGS = [{"digit_bits": d, "block_threads": b, "items_per_thread": i}
-           for d in (4, 8, 9, 11) for b, i in ((256, 8), (256, 16), (512, 8), (512, 16))]
+           for d in (4, 8, 9, 11) for b, i in ((256, 8), (256, 16), (512, 8), (512, 16), (1024, 16))
+           if not (b == 1024 and d > 9)]
 
 
 def test_tunings_identical(lib):
