@@ -260,10 +260,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
             uint32_t mlo = uint32_t(vm), mhi = uint32_t(vm >> 32);
 #pragma unroll
             for (int b = 0; b < D; ++b) {
-                const uint32_t sb = uint32_t(int32_t(dg << (31 - b)) >> 31);
+                uint32_t sb = uint32_t(int32_t(dg << (31 - b)) >> 31);  // all ones iff bit b set
+                asm("" : "+v"(sb));  // keep sb in a register so the ballot compares it directly
                 const uint64_t bb = ballot(sb != 0);
-                mlo &= ~(uint32_t(bb) ^ sb);
-                mhi &= ~(uint32_t(bb >> 32) ^ sb);
+                // keep the lanes whose bit b equals this lane's: m & ~(ballot ^ sb), one v_bitop3
+                // per half (truth table indexed by (m, ballot, sb) bits: 1 at 100b and 111b)
+                mlo = __builtin_amdgcn_bitop3_b32(mlo, uint32_t(bb), sb, 0x90);
+                mhi = __builtin_amdgcn_bitop3_b32(mhi, uint32_t(bb >> 32), sb, 0x90);
             }
             const uint64_t m = (uint64_t(mhi) << 32) | mlo;
             if (valid) {
@@ -489,8 +492,10 @@ __device__ __forceinline__ uint32_t set_of(const int64_t *__restrict__ set_off, 
     return lo;
 }
 
+constexpr int kK0Block = 1024;  // threads per key0 workgroup (grid-stride, one partial each)
+
 template <int D>
-__global__ __launch_bounds__(256) void k_key0(const uint32_t *__restrict__ packed,
+__global__ __launch_bounds__(kK0Block) void k_key0(const uint32_t *__restrict__ packed,
                                               const uint32_t *__restrict__ sepmask, uint32_t n,
                                               uint32_t h0, const int64_t *__restrict__ set_off,
                                               uint32_t n_sets, uint64_t *__restrict__ keys,
@@ -522,10 +527,10 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
     TimedScope ts("keybuild", double(n) * (12.0 + 0.375), s);
     const unsigned g = hist_grid(n);
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_key0<4>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
-        case 8: hipLaunchKernelGGL(k_key0<8>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
-        case 9: hipLaunchKernelGGL(k_key0<9>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
-        case 11: hipLaunchKernelGGL(k_key0<11>, dim3(g), dim3(256), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 4: hipLaunchKernelGGL(k_key0<4>, dim3(g), dim3(kK0Block), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 8: hipLaunchKernelGGL(k_key0<8>, dim3(g), dim3(kK0Block), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 9: hipLaunchKernelGGL(k_key0<9>, dim3(g), dim3(kK0Block), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
+        case 11: hipLaunchKernelGGL(k_key0<11>, dim3(g), dim3(kK0Block), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     ts.finish();
@@ -540,8 +545,8 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
 // has at least h symbols before its separator, so p + h stays inside the text.  The round's
 // active count and h are read from device memory (state[kStActive], state[kStH]); the number
 // of keys written goes to state[kStKeys].
-constexpr int kKbBlock = 256;
-constexpr int kKbItems = 16;
+constexpr int kKbBlock = 512;
+constexpr int kKbItems = 8;
 constexpr int kKbTile = kKbBlock * kKbItems;
 
 template <int D>
