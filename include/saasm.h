@@ -50,7 +50,7 @@ enum {
 };
 
 /* Launch tuning of the radix sort; a zero field means "use the default".
- *   digit_bits       4, 8, 9 or 11 bits per LSD pass
+ *   digit_bits       4, 8, 9 or 11 bits per LSD pass (default 9)
  *   block_threads    256, 512 or 1024 threads per workgroup (4, 8 or 16 wave64 wavefronts;
  *                    1024 only with 16 items and digit_bits <= 9; default 1024, or 512 for
  *                    11-bit digits)

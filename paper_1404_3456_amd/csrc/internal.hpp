@@ -49,7 +49,7 @@ struct Carver {
 
 // ---- tuning --------------------------------------------------------------------------------
 struct Tune {
-    int dbits = 8;
+    int dbits = 9;
     int block = 1024;  // 512 when digits are wider than 9 bits (resolve_tuning)
     int items = 16;
     int tile() const { return block * items; }

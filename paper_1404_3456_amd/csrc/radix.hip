@@ -187,6 +187,45 @@ int launch_hist(const SortBufs &b, int cur, int64_t n, int bit_lo, int bits, con
     return SA_OK;
 }
 
+// Ranks one wave's ITEMS x 64 items by digit, stably: pos[k] = the wave's running count of the
+// item's digit before it (items in index order, k-major, lane-minor).  Each item's peers (the
+// lanes holding the same digit) come from ballots over the digit bits; the lowest peer advances
+// the count in LDS.  FULL: every item is valid (a full tile), so no validity test is made.
+template <int D, int ITEMS, bool FULL, class Cnt>
+__device__ __forceinline__ void rank_wave(const uint64_t (&key)[ITEMS], uint32_t (&pos)[ITEMS],
+                                          uint32_t wbase, uint32_t n, uint32_t lane,
+                                          uint32_t shift, uint32_t dmask, Cnt *wcnt) {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const bool valid = FULL || wbase + k * kWave + lane < n;
+        const uint32_t dg = valid ? (uint32_t(key[k] >> shift) & dmask) : 0u;
+        uint32_t mlo = ~0u, mhi = ~0u;
+        if (!FULL) {
+            const uint64_t vm = ballot(valid);
+            mlo = uint32_t(vm);
+            mhi = uint32_t(vm >> 32);
+        }
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            uint32_t sb = uint32_t(int32_t(dg << (31 - b)) >> 31);  // all ones iff bit b set
+            asm("" : "+v"(sb));  // keep sb in a register so the ballot compares it directly
+            const uint64_t bb = ballot(sb != 0);
+            // keep the lanes whose bit b equals this lane's: m & ~(ballot ^ sb), one v_bitop3
+            // per half (truth table indexed by (m, ballot, sb) bits: 1 at 100b and 111b)
+            mlo = __builtin_amdgcn_bitop3_b32(mlo, uint32_t(bb), sb, 0x90);
+            mhi = __builtin_amdgcn_bitop3_b32(mhi, uint32_t(bb >> 32), sb, 0x90);
+        }
+        // peers in lower lanes: popcount(m & lanes below), by mbcnt
+        const uint32_t r = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
+        if (valid) {
+            const uint32_t c0 = wcnt[dg];
+            pos[k] = c0 + r;
+            if (r == 0) wcnt[dg] = Cnt(c0 + uint32_t(__popc(mlo) + __popc(mhi)));
+        }
+        wave_sync();
+    }
+}
+
 // ---- one LSD pass ---------------------------------------------------------------------------
 // One tile per workgroup, tiles numbered by ticket.  The grid covers an upper bound on the
 // item count; the count itself is read from device memory when `count_dev` is given (so the
@@ -251,32 +290,8 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
 
         // Stable rank of every item among the items of its wave with the same digit: items
         // are taken in index order (k-major, lane-minor), the running count per digit in LDS.
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t idx = wbase + k * kWave + lane;
-            const bool valid = idx < n;
-            const uint32_t dg = valid ? (uint32_t(key[k] >> shift) & dmask) : 0u;
-            const uint64_t vm = ballot(valid);
-            uint32_t mlo = uint32_t(vm), mhi = uint32_t(vm >> 32);
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                uint32_t sb = uint32_t(int32_t(dg << (31 - b)) >> 31);  // all ones iff bit b set
-                asm("" : "+v"(sb));  // keep sb in a register so the ballot compares it directly
-                const uint64_t bb = ballot(sb != 0);
-                // keep the lanes whose bit b equals this lane's: m & ~(ballot ^ sb), one v_bitop3
-                // per half (truth table indexed by (m, ballot, sb) bits: 1 at 100b and 111b)
-                mlo = __builtin_amdgcn_bitop3_b32(mlo, uint32_t(bb), sb, 0x90);
-                mhi = __builtin_amdgcn_bitop3_b32(mhi, uint32_t(bb >> 32), sb, 0x90);
-            }
-            const uint64_t m = (uint64_t(mhi) << 32) | mlo;
-            if (valid) {
-                const uint64_t lt = m & lanemask_lt();
-                const uint32_t c0 = s_wcnt[wave * R + dg];
-                pos[k] = c0 + uint32_t(popc64(lt));
-                if (lt == 0) s_wcnt[wave * R + dg] = Cnt(c0 + uint32_t(popc64(m)));
-            }
-            wave_sync();
-        }
+        if (full) rank_wave<D, ITEMS, true>(key, pos, wbase, n, lane, shift, dmask, s_wcnt + wave * R);
+        else rank_wave<D, ITEMS, false>(key, pos, wbase, n, lane, shift, dmask, s_wcnt + wave * R);
         __syncthreads();
 
         // Per digit: exclusive prefix over waves, and the tile total.
