@@ -325,6 +325,43 @@ def bench_lookup(args, pkg, torch, np):
     }), flush=True)
 
 
+def bench_reconstruct(args, pkg, torch, np):
+    """Cut-and-continue reconstruction: a 5 Mbp random sequence cut twice (cut positions at
+    least 32 apart, ~500-base pieces, ~20,000 fragments, shuffled); one step = index build on
+    the GPU (pack, SA, LCP), copy to the host, and the host search through the index."""
+    from paper_1404_3456_amd import synth
+    text_h, seq, frags = synth.two_cuttings(0, 5_000_000, 500, min_gap=32)
+    dev = torch.device("cuda:0")
+    text = torch.from_numpy(text_h).to(dev)
+    log(f"reconstruct: {len(frags)} fragments, n={text_h.size}")
+    times = []
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sa, isa = pkg.sa_build(text)
+        lcp = pkg.sa_lcp(text, sa, isa)
+        sa_h, isa_h, lcp_h = sa.cpu().numpy(), isa.cpu().numpy(), lcp.cpu().numpy()
+        t1 = time.perf_counter()
+        res = pkg.sa_reconstruct_host(text_h, sa_h, isa_h, lcp_h)
+        t2 = time.perf_counter()
+        if i >= args.warmup:
+            times.append((t1 - t0, t2 - t1))
+    assert res is not None and res[0] == seq, "reconstruction differs from the sequence"
+    idx = float(np.median([a for a, _ in times])) * 1e3
+    srch = float(np.median([b for _, b in times])) * 1e3
+    ms = idx + srch
+    print(json.dumps({
+        "metric": "fragments reconstructed per second (cut and continue through the SA)",
+        "value": round(len(frags) / (ms * 1e-3), 1), "unit": "fragments/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "reconstruct-5Mbp-two-cuttings", "fragments": len(frags),
+                   "n": int(text_h.size), "mean_fragment": 500, "min_gap": 32},
+        "index_ms": round(idx, 3), "host_search_ms": round(srch, 3),
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -344,6 +381,8 @@ def main():
         return bench_serving(args, pkg, torch, np)
     if args.workload == "lookup":
         return bench_lookup(args, pkg, torch, np)
+    if args.workload == "reconstruct":
+        return bench_reconstruct(args, pkg, torch, np)
     if args.workload == "plain-large-5M":
         r = synth.large_plain()
     elif args.workload == "repeat-stress-40M":

@@ -193,6 +193,32 @@ int sa_lookup(const uint8_t *text, int64_t n, const int32_t *sa, const uint8_t *
               void *ws, int64_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------- */
+/* Reconstruction from the fragments of two cuttings ("cut and continue", Sec. III), its       */
+/* prefix tests answered by searching the suffix array (Sec. IV).                            */
+/* ---------------------------------------------------------------------------------------- */
+
+/* sa_reconstruct: HOST function.  The text's reads are the fragments of a sequence S cut twice
+ * at disjoint sets of interior positions, mixed (read i = fragment i).  Starting from a 'fir'
+ * pair (a fragment that is a proper prefix of another: the first pieces of the two cuttings),
+ * the cutting that is behind repeatedly takes a fragment that starts with the remainder (the
+ * part of S known beyond it) or is a proper prefix of the remainder; a dead end goes back to
+ * the last choice.  Pairs are tried by the longer fragment's id, then the shorter's; later
+ * choices in increasing fragment id; the first complete reconstruction is returned.  Candidate
+ * fragments are found by walking the suffix array from the remainder's rank under the running
+ * LCP minimum.
+ *   text_h, n          the fragments, each closed by '$' (no empty fragment), host memory
+ *   sa_h, isa_h, lcp_h  sa_build / sa_lcp results for that text, copied to host memory
+ *   order_h            [m] out: fragment ids in placement order
+ *   rs_h               [rs_cap] out, may be NULL: the reconstructed sequence
+ *   rs_len_h           out: its length
+ *   max_steps          bound on search steps
+ * Returns SA_OK; SA_ERR_NOTFOUND when no reconstruction exists (or max_steps is reached);
+ * SA_ERR_CAPACITY when rs_cap is too small; SA_ERR_INVALID for inconsistent input. */
+int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *sa_h, const int32_t *isa_h,
+                   const int32_t *lcp_h, int32_t *order_h, uint8_t *rs_h, int64_t rs_cap,
+                   int64_t *rs_len_h, int64_t max_steps);
+
+/* ---------------------------------------------------------------------------------------- */
 /* Suffix-prefix overlaps between fragments (Sec. III: a fragment is 'fir' when it is a prefix */
 /* of another; the weighted overlap graph's edge weights are overlap lengths; Sec. IV: the     */
 /* suffix array answers these prefix tests).                                                  */

@@ -32,6 +32,8 @@ from ._abi import (  # noqa: F401
     sa_lcp_ws_bytes,
     sa_lookup,
     sa_lookup_ws_bytes,
+    sa_reconstruct,
+    sa_reconstruct_host,
     sa_overlaps,
     sa_overlaps_ws_bytes,
     sa_pack,

@@ -80,6 +80,7 @@ def load():
         "sa_build_batched": ([P, I64, P, I32, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
         "sa_lcp_ws_bytes": ([I64], I64),
         "sa_lookup_ws_bytes": ([I64, I64], I64),
+        "sa_reconstruct": ([P, I64, P, P, P, P, P, I64, P, I64], ctypes.c_int),
         "sa_lookup": ([P, I64, P, P, P, I64, ctypes.c_int32, P, P, I64, P], ctypes.c_int),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
         "sa_lcp_set_chunk": ([I32], ctypes.c_int),
@@ -307,6 +308,40 @@ def sa_lookup(text, sa, patterns, stream=None):
     _check(lib.sa_lookup(_ptr(t), n, _ptr(sa), _ptr(buf), _ptr(off), total, k, _ptr(out),
                          _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def sa_reconstruct_host(text, sa, isa, lcp, max_steps: int = 10 ** 7):
+    """Cut-and-continue reconstruction (host search) over host numpy arrays: returns
+    (sequence bytes, placement order) or None when no reconstruction exists."""
+    import numpy as np
+    t = np.ascontiguousarray(text, dtype=np.uint8)
+    sa = np.ascontiguousarray(sa, dtype=np.int32)
+    isa = np.ascontiguousarray(isa, dtype=np.int32)
+    lcp = np.ascontiguousarray(lcp, dtype=np.int32)
+    m = int((t == ord("$")).sum())
+    order = np.empty(max(m, 1), dtype=np.int32)
+    rs = np.empty(t.size, dtype=np.uint8)
+    rs_len = ctypes.c_int64(0)
+    P = ctypes.c_void_p
+    rc = load().sa_reconstruct(t.ctypes.data_as(P), t.size, sa.ctypes.data_as(P),
+                               isa.ctypes.data_as(P), lcp.ctypes.data_as(P),
+                               order.ctypes.data_as(P), rs.ctypes.data_as(P), rs.size,
+                               ctypes.byref(rs_len), int(max_steps))
+    if rc == SA_ERR_NOTFOUND:
+        return None
+    _check(rc)
+    return bytes(rs[: rs_len.value]), order[:m].tolist()
+
+
+def sa_reconstruct(text, max_steps: int = 10 ** 7, stream=None):
+    """Builds SA, ISA and LCP of the fragment text on the GPU, then runs the host search."""
+    torch = _torch()
+    t = _dev_text(text)
+    sa, isa = sa_build(t, stream=stream)
+    lcp = sa_lcp(t, sa, isa, stream=stream)
+    torch.cuda.synchronize()
+    return sa_reconstruct_host(t.cpu().numpy(), sa.cpu().numpy(), isa.cpu().numpy(),
+                               lcp.cpu().numpy(), max_steps)
 
 
 def sa_lcp_set_chunk(chunk: int):

@@ -297,3 +297,25 @@ def lookup_patterns(text: np.ndarray, count: int, seed: int, len_lo: int = 0,
         cut = s.find(b"$")
         out.append(s if cut < 0 else s[:cut])
     return out
+
+
+def two_cuttings(seed: int, length: int, mean_frag: int, alphabet: bytes = b"ACGT",
+                 min_gap: int = 1):
+    """A random sequence cut twice at disjoint sets of interior positions (the setting of the
+    cut-and-continue reconstruction): returns (text of the shuffled fragments joined with '$',
+    the sequence, the fragments in text order).  Each cutting has about length/mean_frag
+    pieces; no interior cut position is shared, and all cut positions of both cuttings lie on
+    multiples of ``min_gap`` (so every fragment has at least that many bases)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, 13, seed])))
+    seq = bytes(rng.choice(list(alphabet), size=length).astype(np.uint8))
+    k = max(1, length // mean_frag - 1)
+    slots = np.arange(1, (length - 1) // min_gap + 1) * min_gap
+    pos = rng.choice(slots, size=min(2 * k, slots.size), replace=False)
+    a, b = np.sort(pos[: len(pos) // 2]), np.sort(pos[len(pos) // 2:])
+    frags = []
+    for cuts in (a, b):
+        edges = [0] + [int(c) for c in cuts] + [length]
+        frags += [seq[x:y] for x, y in zip(edges, edges[1:])]
+    perm = rng.permutation(len(frags))
+    frags = [frags[i] for i in perm]
+    return text_from_strings([f.decode() for f in frags]), seq, frags

@@ -352,3 +352,35 @@ def test_lookup_rejects_bad_patterns(lib):
     with pytest.raises(lib.SaasmError) as e:
         lib.sa_lookup(t, sa, (buf, off))
     assert e.value.code == lib.SA_ERR_INVALID
+
+
+# ---- cut-and-continue reconstruction over the GPU-built index ------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_reconstruct_vs_oracle(lib, seed):
+    from oracle import recon
+    _, seq, frags = synth.two_cuttings(seed, 20_000, 100, min_gap=16)
+    got = lib.sa_reconstruct(synth.text_from_strings(frags))
+    assert got == recon.reconstruct(frags) and got[0] == seq
+    _, _, frags = synth.two_cuttings(seed, 3000, 50)  # short pieces: several answers
+    assert lib.sa_reconstruct(synth.text_from_strings(frags)) == recon.reconstruct(frags)
+
+
+def test_reconstruct_backtracking_and_unsolvable(lib):
+    assert lib.sa_reconstruct(synth.text_from_strings([b"AC", b"ACGT", b"ACA", b"CGT"])) == \
+        (b"ACACGT", [0, 2, 1, 3])
+    assert lib.sa_reconstruct(synth.text_from_strings([b"AC", b"GT", b"TT"])) is None
+
+
+def test_reconstruct_large_ground_truth(lib):
+    """2 Mbp cut twice into ~8,000 fragments: the original sequence comes back, and the
+    placement order tiles it with both cuttings."""
+    _, seq, frags = synth.two_cuttings(7, 2_000_000, 500, min_gap=32)
+    rs, order = lib.sa_reconstruct(synth.text_from_strings(frags))
+    assert rs == seq and sorted(order) == list(range(len(frags)))
+    e = [0, 0]
+    for f in order:
+        c = 0 if e[0] <= e[1] else 1
+        assert rs[e[c]:e[c] + len(frags[f])] == frags[f]
+        e[c] += len(frags[f])
+    assert e == [len(seq), len(seq)]
