@@ -362,6 +362,36 @@ def bench_reconstruct(args, pkg, torch, np):
     }), flush=True)
 
 
+def bench_overlaps_rc(args, pkg, torch, np):
+    """Overlaps on both strands: 100,000 error-free reads of 500 bp from both strands of a
+    5 Mbp genome (10x); one step = doubled text (reads + reverse complements, N = 100.2 M),
+    SA, LCP, overlaps and strand naming, input resident in HBM."""
+    from paper_1404_3456_amd import synth
+    text_h, _, _ = synth.strand_reads(0, 5_000_000, 100_000, 500)
+    dev = torch.device("cuda:0")
+    text = torch.from_numpy(text_h).to(dev)
+    for _ in range(args.warmup):
+        pkg.sa_overlaps_rc(text, 40)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rows = pkg.sa_overlaps_rc(text, 40)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    n2 = 2 * text_h.size
+    print(json.dumps({
+        "metric": "both-strand overlap step, suffixes of the doubled text per second",
+        "value": round(n2 / (ms * 1e-3) / 1e6, 3), "unit": "Msuffixes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "overlaps-rc-5Mbp-100k-reads", "n": int(text_h.size),
+                   "n_doubled": int(n2), "reads": 100_000, "read_len": 500, "min_overlap": 40,
+                   "rows": int(rows.shape[0]),
+                   "rows_by_strand": [int((rows[:, 2] == k).sum().item()) for k in range(3)]},
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -383,6 +413,8 @@ def main():
         return bench_lookup(args, pkg, torch, np)
     if args.workload == "reconstruct":
         return bench_reconstruct(args, pkg, torch, np)
+    if args.workload == "overlaps-rc":
+        return bench_overlaps_rc(args, pkg, torch, np)
     if args.workload == "plain-large-5M":
         r = synth.large_plain()
     elif args.workload == "repeat-stress-40M":

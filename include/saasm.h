@@ -11,8 +11,8 @@
  *    library never allocates device memory inside these calls and never frees caller memory.
  *    Workspace contents are scratch: nothing is carried from one call to the next.
  *  - Streams: every call is ordered on `stream`.  Calls that report a count or status to the
- *    host (sa_build, sa_overlaps, sa_lookup, sa_pack, sa_sort_pairs) synchronise `stream`
- *    before they return; sa_lcp does not.
+ *    host (sa_build, sa_overlaps, sa_lookup, sa_pack, sa_sort_pairs, sa_revcomp_text,
+ *    sa_strand_rows) synchronise `stream` before they return; sa_lcp does not.
  *  - Errors: every call returns an int status (SA_OK or a negative SA_ERR_*) and never throws
  *    across the ABI.  sa_last_error() returns a message for the calling thread's last failure.
  *    On error the outputs are unspecified; inputs are never modified.
@@ -242,6 +242,33 @@ int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t
                 const int32_t *lcp, int32_t min_len, int32_t *out, int64_t cap,
                 int64_t *n_out_h, void *ws, int64_t ws_bytes, int64_t *ws_needed_h,
                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Overlaps on both strands (Sec. III: the second fragment of an overlap may be reversed and   */
+/* complemented).  Index the doubled text made by sa_revcomp_text with sa_build / sa_lcp /     */
+/* sa_overlaps, then name the rows by strand with sa_strand_rows.                             */
+/* ---------------------------------------------------------------------------------------- */
+
+/* sa_revcomp_text: out[0, n) = text; out[n, 2n) = the reverse complement (A<->T, C<->G) of
+ * text[0, n-1) followed by '$' -- so read m+k of the doubled text is the reverse complement of
+ * read m-1-k.  *m_h = number of reads of text.  out is [2n] device; ws >= 256 bytes.
+ * SA_ERR_TOO_LARGE when 2n >= 2^31 - 2.  Synchronises the stream. */
+int sa_revcomp_text(const uint8_t *text, int64_t n, uint8_t *out, int64_t *m_h, void *ws,
+                    int64_t ws_bytes, hipStream_t stream);
+
+int64_t sa_strand_rows_ws_bytes(int64_t rows, int64_t m);
+
+/* sa_strand_rows: rows [r][3] = sa_overlaps output on a doubled text of 2m reads.  Writes
+ * out [cap][4] int32 rows (a, b, strand, l), a != b, sorted by (a, b, strand), naming the
+ * original reads a and b and how the overlap of length l joins them:
+ *   strand 0: the last l bases of a equal the first l of b;
+ *   strand 1: the last l bases of a equal the first l of rc(b)  (their ends meet);
+ *   strand 2: the last l bases of rc(a) equal the first l of b  (their starts meet).
+ * (rc(a) before rc(b) is b before a, a strand-0 row.)  *n_out_h = number of rows
+ * (SA_ERR_CAPACITY when cap is smaller).  SA_ERR_INVALID for a read id >= 2m.  Synchronises
+ * the stream. */
+int sa_strand_rows(const int32_t *rows, int64_t r, int64_t m, int32_t *out, int64_t cap,
+                   int64_t *n_out_h, void *ws, int64_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Assembly-job server: continuous batching of fragment sets (Sec. III: one set of shotgun     */

@@ -168,3 +168,29 @@ def lookup(text, patterns, nthreads=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("pattern holds a separator, or bad text")
     return out[: len(pats)]
+
+
+_COMP = np.arange(256, dtype=np.uint8)
+for _x, _y in ((b"A", b"T"), (b"C", b"G"), (b"G", b"C"), (b"T", b"A")):
+    _COMP[_x[0]] = _y[0]
+
+
+def overlaps_rc(text, min_len, nthreads=None) -> np.ndarray:
+    """Overlaps on both strands: (k, 4) int32 rows (a, b, strand, l), a != b, sorted by
+    (a, b, strand): strand 0 = a then b, 1 = a then the reverse complement of b, 2 = the reverse
+    complement of a then b.  Computed as the forward overlaps of the text followed by every
+    read's reverse complement (read m+k is the reverse complement of read m-1-k); a row of two
+    reverse complements repeats a strand-0 row and is dropped."""
+    t = _text(text)
+    m = int((t == ord("$")).sum())
+    doubled = np.concatenate([t, _COMP[t[:-1][::-1]], np.array([ord("$")], dtype=np.uint8)])
+    rows = overlaps(doubled, min_len, nthreads).astype(np.int64)
+    x, y, l = rows[:, 0], rows[:, 1], rows[:, 2]
+    xf, yf = x < m, y < m
+    a = np.where(xf, x, 2 * m - 1 - x)
+    b = np.where(yf, y, 2 * m - 1 - y)
+    strand = np.where(xf, np.where(yf, 0, 1), 2)
+    keep = (xf | yf) & (a != b)
+    out = np.stack([a, b, strand, l], axis=1)[keep]
+    order = np.lexsort((out[:, 2], out[:, 1], out[:, 0]))
+    return out[order].astype(np.int32)

@@ -70,3 +70,29 @@ def lookup(text: bytes, pattern: bytes):
         lo = sum(1 for p in range(len(s)) if s[p:] < pat)
         return lo, lo
     return hits[0], hits[-1] + 1
+
+
+_COMP = {ord("A"): ord("T"), ord("C"): ord("G"), ord("G"): ord("C"), ord("T"): ord("A")}
+
+
+def revcomp(read: bytes) -> bytes:
+    return bytes(_COMP.get(c, c) for c in reversed(read))
+
+
+def overlaps_rc(text: bytes, min_len: int):
+    """Both strands, literally: for reads a != b and each of the three ways two reads can
+    meet -- (A, B) = (a, b) [strand 0], (a, revcomp(b)) [1], (revcomp(a), b) [2] -- the
+    largest l with min_len <= l <= min(|A|, |B|) such that the last l bases of A equal the
+    first l of B; rows [a, b, strand, l] sorted."""
+    rs = reads(text)
+    out = []
+    for a, ra in enumerate(rs):
+        for b, rb in enumerate(rs):
+            if a == b:
+                continue
+            for o, (A, B) in enumerate(((ra, rb), (ra, revcomp(rb)), (revcomp(ra), rb))):
+                for l in range(min(len(A), len(B)), min_len - 1, -1):
+                    if l > 0 and A[len(A) - l:] == B[:l]:
+                        out.append([a, b, o, l])
+                        break
+    return out

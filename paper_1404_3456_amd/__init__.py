@@ -34,6 +34,9 @@ from ._abi import (  # noqa: F401
     sa_lookup_ws_bytes,
     sa_reconstruct,
     sa_reconstruct_host,
+    sa_revcomp_text,
+    sa_strand_rows,
+    sa_overlaps_rc,
     sa_overlaps,
     sa_overlaps_ws_bytes,
     sa_pack,

@@ -81,6 +81,9 @@ def load():
         "sa_lcp_ws_bytes": ([I64], I64),
         "sa_lookup_ws_bytes": ([I64, I64], I64),
         "sa_reconstruct": ([P, I64, P, P, P, P, P, I64, P, I64], ctypes.c_int),
+        "sa_revcomp_text": ([P, I64, P, P, P, I64, P], ctypes.c_int),
+        "sa_strand_rows_ws_bytes": ([I64, I64], I64),
+        "sa_strand_rows": ([P, I64, I64, P, I64, P, P, I64, P], ctypes.c_int),
         "sa_lookup": ([P, I64, P, P, P, I64, ctypes.c_int32, P, P, I64, P], ctypes.c_int),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
         "sa_lcp_set_chunk": ([I32], ctypes.c_int),
@@ -342,6 +345,42 @@ def sa_reconstruct(text, max_steps: int = 10 ** 7, stream=None):
     torch.cuda.synchronize()
     return sa_reconstruct_host(t.cpu().numpy(), sa.cpu().numpy(), isa.cpu().numpy(),
                                lcp.cpu().numpy(), max_steps)
+
+
+def sa_revcomp_text(text, stream=None):
+    """(doubled device text: reads then their reverse complements, number of reads m)."""
+    torch = _torch()
+    t = _dev_text(text)
+    n = t.numel()
+    out = torch.empty(2 * n, dtype=torch.uint8, device=t.device)
+    ws = _ws(256, t.device)
+    m = ctypes.c_int64(0)
+    _check(load().sa_revcomp_text(_ptr(t), n, _ptr(out), ctypes.byref(m), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return out, int(m.value)
+
+
+def sa_strand_rows(rows, m: int, stream=None):
+    """(k, 4) int32 rows (a, b, strand, l) from the (r, 3) overlaps of a doubled text."""
+    torch = _torch()
+    rows = rows.contiguous()
+    r = rows.shape[0]
+    ws = _ws(int(load().sa_strand_rows_ws_bytes(r, m)), rows.device)
+    cap = max(r, 1)
+    out = torch.empty((cap, 4), dtype=torch.int32, device=rows.device)
+    n_out = ctypes.c_int64(0)
+    _check(load().sa_strand_rows(_ptr(rows), r, m, _ptr(out), cap, ctypes.byref(n_out), _ptr(ws),
+                                 ws.numel(), _stream(stream)))
+    return out[: n_out.value]
+
+
+def sa_overlaps_rc(text, min_len: int, stream=None):
+    """Overlaps on both strands: (k, 4) int32 device rows (a, b, strand, l), sorted."""
+    t2, m = sa_revcomp_text(text, stream=stream)
+    sa, isa = sa_build(t2, stream=stream)
+    lcp = sa_lcp(t2, sa, isa, stream=stream)
+    rows = sa_overlaps(t2, sa, isa, lcp, min_len, stream=stream)
+    return sa_strand_rows(rows, m, stream=stream)
 
 
 def sa_lcp_set_chunk(chunk: int):

@@ -319,3 +319,22 @@ def two_cuttings(seed: int, length: int, mean_frag: int, alphabet: bytes = b"ACG
     perm = rng.permutation(len(frags))
     frags = [frags[i] for i in perm]
     return text_from_strings([f.decode() for f in frags]), seq, frags
+
+
+def strand_reads(seed: int, g: int, m: int, read_len: int):
+    """Error-free reads of one random genome taken from either strand: returns (text, starts,
+    strands) with strand 1 meaning the read is the reverse complement of
+    genome[start:start+read_len].  For ground-truth checks of overlaps on both strands."""
+    rng_g, rng_s = [np.random.Generator(np.random.PCG64(c))
+                    for c in np.random.SeedSequence([SEED_BASE, 17, seed]).spawn(2)]
+    genome = rng_g.integers(0, 4, size=g, dtype=np.uint8)
+    starts = rng_s.integers(0, g - read_len + 1, size=m)
+    strands = rng_s.integers(0, 2, size=m)
+    letters = np.frombuffer(b"ACGT", dtype=np.uint8)
+    reads = []
+    for s, d in zip(starts.tolist(), strands.tolist()):
+        codes = genome[s:s + read_len]
+        if d:
+            codes = 3 - codes[::-1]  # A<->T, C<->G under the code order A C G T
+        reads.append(bytes(letters[codes]))
+    return text_from_strings(reads), starts, strands

@@ -122,3 +122,27 @@ def swap_pairs(ovl) -> np.ndarray:
     sw = ovl[:, [1, 0, 2]]
     order = np.lexsort((sw[:, 1], sw[:, 0]))
     return sw[order]
+
+
+def positional_overlaps_rc(starts, strands, read_len, min_len):
+    """Ground truth on both strands for error-free equal-length reads: read x covers genome
+    [s_x, s_x + L) in orientation d_x (+1 forward, -1 reverse).  For a != b and each way of
+    meeting -- (A, B) = (a, b), (a, rc b), (rc a, b) -- A's suffix meets B's prefix when A and
+    B run the same way and B starts 0 <= e <= L - min_len bases after A along that direction,
+    overlap L - e."""
+    starts = np.asarray(starts, dtype=np.int64)
+    d = np.where(np.asarray(strands) == 1, -1, 1)
+    m = starts.size
+    out = []
+    for a in range(m):
+        for b in range(m):
+            if a == b:
+                continue
+            for o, (da, db) in enumerate(((d[a], d[b]), (d[a], -d[b]), (-d[a], d[b]))):
+                if da != db:
+                    continue
+                e = (starts[b] - starts[a]) * da
+                if 0 <= e <= read_len - min_len:
+                    out.append((a, b, o, int(read_len - e)))
+    out.sort()
+    return np.asarray(out, dtype=np.int32).reshape(-1, 4)

@@ -384,3 +384,36 @@ def test_reconstruct_large_ground_truth(lib):
         assert rs[e[c]:e[c] + len(frags[f])] == frags[f]
         e[c] += len(frags[f])
     assert e == [len(seq), len(seq)]
+
+
+# ---- overlaps on both strands --------------------------------------------------------------
+
+def test_revcomp_text_layout(lib):
+    text = synth.random_dna_reads(80, 50, 0, 40, allow_empty=True)
+    t2, m = lib.sa_revcomp_text(dev(text))
+    comp = np.arange(256, dtype=np.uint8)
+    for x, y in (("A", "T"), ("C", "G"), ("G", "C"), ("T", "A")):
+        comp[ord(x)] = ord(y)
+    want = np.concatenate([text, comp[text[:-1][::-1]], np.array([ord("$")], dtype=np.uint8)])
+    assert np.array_equal(t2.cpu().numpy(), want) and m == int((text == ord("$")).sum())
+
+
+@pytest.mark.parametrize("case", ["strand_reads", "ragged", "edge"])
+def test_overlaps_rc_vs_oracle(lib, case):
+    if case == "strand_reads":
+        texts = [(synth.strand_reads(1, 20_000, 400, 200)[0], 30)]
+    elif case == "ragged":
+        texts = [(synth.random_dna_reads(90 + s, 400, 0, 120, allow_empty=True), 8) for s in range(2)]
+    else:
+        texts = [(np.frombuffer(EDGE[k], dtype=np.uint8).copy(), 1) for k in sorted(EDGE)]
+    for text, ml in texts:
+        got = lib.sa_overlaps_rc(dev(text), ml).cpu().numpy()
+        assert np.array_equal(got, oracle.overlaps_rc(text, ml)), (case, text.size)
+
+
+def test_overlaps_rc_sampled_large(lib):
+    """A 10 M-character sample of the plain large workload (doubled to 20 M)."""
+    r = synth.large_plain(scale=0.2)
+    got = lib.sa_overlaps_rc(dev(r.text), r.min_len).cpu().numpy()
+    want = oracle.overlaps_rc(r.text, r.min_len)
+    assert got.shape[0] > 1000 and np.array_equal(got, want)

@@ -297,6 +297,38 @@ def test_lookup_rejects_separator_in_pattern():
         oracle.lookup(b"ACGT$", [b"A$"])
 
 
+# ---- overlaps on both strands ----------------------------------------------------------------
+
+def test_overlaps_rc_vs_brute():
+    for t in TINY[::23]:
+        for ml in (1, 2):
+            assert oracle.overlaps_rc(t, ml).tolist() == brute.overlaps_rc(t, ml), (t, ml)
+    for seed in range(3):
+        t = bytes(synth.random_dna_reads(60 + seed, 25, 1, 14))
+        assert oracle.overlaps_rc(t, 3).tolist() == brute.overlaps_rc(t, 3)
+
+
+def test_overlaps_rc_strand_symmetry():
+    """Ends meeting (strand 1) and starts meeting (strand 2) are symmetric in a and b: the last
+    l bases of a equal the first l of revcomp(b) exactly when the same holds with a and b
+    swapped, and likewise for revcomp(a) before b."""
+    t = bytes(synth.random_dna_reads(70, 300, 20, 80))
+    rows = oracle.overlaps_rc(t, 5).tolist()
+    for o in (1, 2):
+        s = {(a, b, l) for a, b, oo, l in rows if oo == o}
+        assert s and s == {(b, a, l) for a, b, l in s}, o
+
+
+def test_overlaps_rc_positional_ground_truth():
+    """Error-free reads from both strands of a random genome: every overlap is the one their
+    genome positions and orientations imply."""
+    text, starts, strands = synth.strand_reads(0, 20_000, 400, 200)
+    got = oracle.overlaps_rc(text, 30)
+    want = checks.positional_overlaps_rc(starts, strands, 200, 30)
+    assert np.array_equal(got, want)
+    assert (got[:, 2] == 1).sum() > 100 and (got[:, 2] == 2).sum() > 100
+
+
 # ---- planted mistakes: each mutant of the C oracle must fail some pin --------------------
 
 MUTANTS = {
