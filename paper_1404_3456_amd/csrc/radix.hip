@@ -322,19 +322,15 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
         for (int j = 0; j < DPT; ++j) tsum += tot[j];
         uint32_t tile_total;
         uint32_t run = block_excl_sum<BLOCK>(tsum, s_scan, &tile_total);
+        // Local digit starts first: the tile is staged in digit order while the digit owners
+        // look back for the global offsets (only the final scatter needs those).
+        uint32_t lstart[DPT];
 #pragma unroll
         for (int j = 0; j < DPT; ++j) {
             const int d = tid * DPT + j;
-            if (d < R) {
-                uint32_t ex = 0;
-                if (tile > 0) {
-                    ex = lookback_digit(flags, int(tile), R, d, err);
-                    st_agent(myflags + d, lb32_word(true, ex + tot[j]));
-                }
-                s_lstart[d] = run;
-                s_gofs[d] = gbase[d] + ex - run;
-                run += tot[j];
-            }
+            lstart[j] = run;
+            if (d < R) s_lstart[d] = run;
+            run += tot[j];
         }
         __syncthreads();
 
@@ -347,6 +343,18 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(const uint64_t *__restrict__
                 const uint32_t lp = s_lstart[dg] + uint32_t(s_wcnt[wave * R + dg]) + pos[k];
                 s_stage[lp] = key[k];
                 pos[k] = lp;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            if (d < R) {
+                uint32_t ex = 0;
+                if (tile > 0) {
+                    ex = lookback_digit(flags, int(tile), R, d, err);
+                    st_agent(myflags + d, lb32_word(true, ex + tot[j]));
+                }
+                s_gofs[d] = gbase[d] + ex - lstart[j];
             }
         }
         __syncthreads();
