@@ -28,17 +28,19 @@ def valid_two_cuttings(frags):
 
 
 def is_valid(frags, rs, order):
-    """The returned placement order splits into the two cuttings: fragments tile rs in the
-    given order when each is assigned to the cutting that is behind."""
+    """The placement order uses every fragment once and splits into two cuttings that both tile
+    rs (each fragment goes to the cutting that is behind) with no interior cut in common."""
     e = [0, 0]
-    for i, f in enumerate(order):
+    cuts = [set(), set()]
+    for f in order:
         c = 0 if e[0] <= e[1] else 1
         s = frags[f]
         if rs[e[c]:e[c] + len(s)] != s:
             return False
         e[c] += len(s)
-    cuts_ok = True
-    return sorted(order) == list(range(len(frags))) and e[0] == e[1] == len(rs) and cuts_ok
+        cuts[c].add(e[c])
+    interior = (cuts[0] & cuts[1]) - {len(rs)}
+    return sorted(order) == list(range(len(frags))) and e[0] == e[1] == len(rs) and not interior
 
 
 def tiny_instances(count, seed):
