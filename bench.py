@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
     ap.add_argument("--lcp-chunk", type=int, default=0)
+    ap.add_argument("--sa-algo", choices=("doubling", "dc3"), default="doubling",
+                    help="suffix-array construction of the timed path: prefix doubling "
+                         "(sa_build) or the skew recursion (sa_build_dc3); same array")
     ap.add_argument("--max-total", type=int, default=0,
                     help="batched workload: stop adding sets once this many characters are drawn")
     ap.add_argument("--graph", action="store_true",
@@ -438,8 +441,13 @@ def main():
     n = r.n
     stream = torch.cuda.current_stream()
 
+    def build_sa():
+        if args.sa_algo == "dc3":
+            return pkg.sa_build_dc3(text, tuning=tuning, return_levels=True)
+        return pkg.sa_build(text, tuning=tuning, return_rounds=True)
+
     def step():
-        sa, isa = pkg.sa_build(text, tuning=tuning)
+        sa, isa, _ = build_sa()
         lcp = pkg.sa_lcp(text, sa, isa)
         ovl = pkg.sa_overlaps(text, sa, isa, lcp, r.min_len)
         return sa, isa, lcp, ovl
@@ -464,7 +472,7 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        sa, isa, rounds = pkg.sa_build(text, tuning=tuning, return_rounds=True)
+        sa, isa, rounds = build_sa()
         e1.record(stream)
         lcp = pkg.sa_lcp(text, sa, isa)
         ovl = pkg.sa_overlaps(text, sa, isa, lcp, r.min_len)
@@ -477,7 +485,11 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
 
     kern = {}
-    for key in ("radix_pass", "keybuild", "rank_update", "kasai", "overlap_walk", "pack"):
+    keys = ("radix_pass", "keybuild", "rank_update", "kasai", "overlap_walk", "pack")
+    if args.sa_algo == "dc3":
+        keys = ("radix_pass", "dc3_keys", "dc3_names", "dc3_lift", "dc3_merge", "kasai",
+                "overlap_walk", "pack")
+    for key in keys:
         L, ms, by = pkg.sa_timing_get(key)
         kern[key] = {"launches": L, "ms": round(ms, 4),
                      "avg_us": round(ms * 1000.0 / L, 3) if L else None,
@@ -493,7 +505,7 @@ def main():
                            open(os.path.join(csrc, "device.hpp"), "rb").read()).hexdigest()
         try:
             tr = json.load(open(args.traffic))
-            if tr.get("source_sha256") == h and (tuning is None):
+            if tr.get("source_sha256") == h and tuning is None and args.sa_algo == "doubling":
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -529,7 +541,8 @@ def main():
                    "sha256": r.sha256(), "tuning": tuning.__dict__ if tuning else "default"},
         "sa_build_ms": round(sa_build_ms, 3),
         "sa_build_Msuffixes_per_s": round(n / (sa_build_ms * 1e-3) / 1e6, 3),
-        "sa_rounds": rounds,
+        "sa_algorithm": args.sa_algo,
+        ("sa_levels" if args.sa_algo == "dc3" else "sa_rounds"): rounds,
         "kernels": kern,
         "roofline": roofline,
         "cpu_baseline": cpu,

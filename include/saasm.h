@@ -130,6 +130,20 @@ int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
              void *ws, int64_t ws_bytes, const sa_tuning *tune_or_null, int32_t *rounds_h,
              hipStream_t stream);
 
+/* The same suffix array by the skew recursion over the difference cover {1, 2} mod 3 (the
+ * linear-work construction of Kärkkäinen, Sanders and Burkhardt that Sec. IV cites and names
+ * its radix-sort kernel after): the samples (positions not 0 mod 3) are sorted by their first
+ * three symbols with the radix passes of sa_sort_pairs and named, the string of names is
+ * sorted recursively while two samples share a name, the other suffixes are sorted by
+ * (symbol, rank of the next suffix), and the two lists are merged.  Arguments, layout and
+ * errors are those of sa_build; the output is identical to sa_build's.
+ *   levels_h     optional host out: number of recursion levels run (1 = no recursion)
+ * Synchronises the stream once per level. */
+int64_t sa_build_dc3_ws_bytes(int64_t n, const sa_tuning *tune_or_null);
+int sa_build_dc3(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
+                 void *ws, int64_t ws_bytes, const sa_tuning *tune_or_null, int32_t *levels_h,
+                 hipStream_t stream);
+
 /* Batched build of many independent texts in one set of launches (the fragment sets of
  * Sec. III, one per assembly job).  The texts are laid end to end in `text`; text s occupies
  * text[set_off_h[s] .. set_off_h[s+1]) and must end with '$'.

@@ -25,6 +25,8 @@ from ._abi import (  # noqa: F401
     sa_build,
     sa_build_batched,
     sa_build_batched_ws_bytes,
+    sa_build_dc3,
+    sa_build_dc3_ws_bytes,
     sa_build_ws_bytes,
     sa_copy_u32,
     sa_lcp,

@@ -76,6 +76,8 @@ def load():
         "sa_sort_pairs": ([P, P, I64, I32, I32, P, I64, TP, P], ctypes.c_int),
         "sa_build_ws_bytes": ([I64, TP], I64),
         "sa_build": ([P, I64, P, P, P, I64, TP, P, P], ctypes.c_int),
+        "sa_build_dc3_ws_bytes": ([I64, TP], I64),
+        "sa_build_dc3": ([P, I64, P, P, P, I64, TP, P, P], ctypes.c_int),
         "sa_build_batched_ws_bytes": ([I64, I32, P, TP], I64),
         "sa_build_batched": ([P, I64, P, I32, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
         "sa_lcp_ws_bytes": ([I64], I64),
@@ -168,6 +170,10 @@ def sa_build_ws_bytes(n: int, tuning=None) -> int:
     return int(load().sa_build_ws_bytes(n, _tune(tuning)))
 
 
+def sa_build_dc3_ws_bytes(n: int, tuning=None) -> int:
+    return int(load().sa_build_dc3_ws_bytes(n, _tune(tuning)))
+
+
 def sa_lcp_ws_bytes(n: int) -> int:
     return int(load().sa_lcp_ws_bytes(n))
 
@@ -233,6 +239,26 @@ def sa_build(text, isa: bool = True, tuning=None, stream=None, return_rounds: bo
                         ctypes.byref(rounds), _stream(stream)))
     if return_rounds:
         return sa, isa_t, int(rounds.value)
+    return sa, isa_t
+
+
+def sa_build_dc3(text, isa: bool = True, tuning=None, stream=None, return_levels: bool = False):
+    """The same suffix array (and inverse) by the skew recursion (sa_build_dc3)."""
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    sa = torch.empty(n, dtype=torch.int32, device=t.device)
+    isa_t = torch.empty(n, dtype=torch.int32, device=t.device) if isa else None
+    wsb = sa_build_dc3_ws_bytes(n, tuning)
+    if wsb < 0:
+        raise SaasmError(SA_ERR_INVALID, "bad size or tuning")
+    ws = _ws(wsb, t.device)
+    levels = ctypes.c_int32(0)
+    _check(lib.sa_build_dc3(_ptr(t), n, _ptr(sa), _ptr(isa_t), _ptr(ws), ws.numel(),
+                            _tune(tuning), ctypes.byref(levels), _stream(stream)))
+    if return_levels:
+        return sa, isa_t, int(levels.value)
     return sa, isa_t
 
 

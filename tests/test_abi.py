@@ -90,6 +90,26 @@ def test_host_argument_checks_without_gpu():
                          16, None) == _abi.SA_ERR_NOMEM
 
 
+def test_dc3_host_checks_and_workspace():
+    lib = _abi.load()
+    dummy = ctypes.c_void_p(16)
+    assert lib.sa_build_dc3(None, 10, None, None, None, 0, None, None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_build_dc3(dummy, 0, dummy, None, dummy, 1 << 20, None, None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_build_dc3(dummy, (1 << 31) - 2, dummy, None, dummy, 1 << 20, None, None,
+                            None) == _abi.SA_ERR_TOO_LARGE
+    assert lib.sa_build_dc3(dummy, 100, dummy, None, dummy, 16, None, None, None) == _abi.SA_ERR_NOMEM
+    assert "workspace" in _abi.sa_last_error()
+    bad = _abi.Tuning(digit_bits=7).c()
+    assert lib.sa_build_dc3(dummy, 100, dummy, None, dummy, 1 << 30, ctypes.byref(bad), None,
+                            None) == _abi.SA_ERR_INVALID
+    assert _abi.sa_build_dc3_ws_bytes(0) == -1
+    assert _abi.sa_build_dc3_ws_bytes(1) > 0
+    big = _abi.sa_build_dc3_ws_bytes(50_100_000)
+    # per suffix: ranks, samples and name strings over the shrinking levels, plus the sort
+    # buffers for two thirds of the suffixes
+    assert 30 * 50_100_000 < big < 70 * 50_100_000
+
+
 def test_default_tile_for_wide_digits_is_accepted():
     """11-bit digits with the tile left at its default resolve to a 512-thread tile (workspace
     sizing goes through the same resolution, so a size comes back instead of an error)."""
