@@ -487,7 +487,7 @@ def main():
     kern = {}
     keys = ("radix_pass", "keybuild", "rank_update", "kasai", "overlap_walk", "pack")
     if args.sa_algo == "dc3":
-        keys = ("radix_pass", "dc3_keys", "dc3_names", "dc3_lift", "dc3_merge", "kasai",
+        keys = ("radix_pass", "dc3_keys", "dc3_names", "dc3_lift", "dc3_recs", "dc3_merge", "kasai",
                 "overlap_walk", "pack")
     for key in keys:
         L, ms, by = pkg.sa_timing_get(key)

@@ -121,39 +121,95 @@ __global__ __launch_bounds__(kD3Block) void k_d3_rekey(const uint32_t *__restric
 }
 
 // ---- step 1: names ------------------------------------------------------------------------
-// flags[j] = 1 when sorted sample j starts a new name.
+constexpr int kNsItems = 16;                      // sorted samples per thread of the name scan
+constexpr int kNsTile = kD3Block * kNsItems;
+
+// Names in sorted order: nm[j] = number of distinct triples among sorted samples 0..j.  A
+// sample starts a new name when its key differs from its predecessor's (at the top level also
+// when its triple holds a separator; with two sorts also when the last names differ).  One
+// pass: head flags, a workgroup scan and a decoupled look-back over tiles; the last tile
+// writes the name count to *total.  A tile is kNsItems rows of kD3Block consecutive samples,
+// each row read and written by the whole workgroup (coalesced); a row's heads are counted
+// with one ballot per wave.
 template <bool TOP>
-__global__ __launch_bounds__(kD3Block) void k_d3_heads(const uint64_t *__restrict__ keys,
-                                                       const uint32_t *__restrict__ vals,
-                                                       const uint32_t *__restrict__ s,
-                                                       uint32_t n12, int two_sort,
-                                                       uint32_t *__restrict__ flags) {
-    for (uint32_t j = blockIdx.x * kD3Block + threadIdx.x; j < n12; j += gridDim.x * kD3Block) {
-        const uint64_t k = keys[j];
-        bool head = j == 0 || k != keys[j - 1];
-        if constexpr (TOP) {
-            head = head || (k & 7u) == 0;  // holds a separator
-        } else {
-            if (!head && two_sort) head = s[vals[j] + 2] != s[vals[j - 1] + 2];
+__global__ __launch_bounds__(kD3Block) void k_d3_name_scan(const uint64_t *__restrict__ keys,
+                                                           const uint32_t *__restrict__ vals,
+                                                           const uint32_t *__restrict__ s,
+                                                           uint32_t n12, int two_sort,
+                                                           uint32_t *__restrict__ nm,
+                                                           uint32_t *total, uint64_t *lbflags,
+                                                           uint32_t *tick, uint32_t *err) {
+    constexpr int W = kD3Block / kWave;
+    __shared__ uint32_t s_tile, s_excl;
+    __shared__ uint32_t s_cnt[kNsItems][W];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    if (tid == 0) s_tile = ticket(tick);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * uint32_t(kNsTile) + tid;
+    uint32_t heads = 0;
+    uint32_t below[kNsItems];  // heads of lower lanes of this wave in the same row
+#pragma unroll
+    for (int r = 0; r < kNsItems; ++r) {
+        const uint32_t i = base + uint32_t(r) * kD3Block;
+        bool head = false;
+        if (i < n12) {
+            const uint64_t k = keys[i];
+            head = i == 0 || k != keys[i - 1];
+            if constexpr (TOP) head = head || (k & 7u) == 0;  // holds a separator
+            else if (two_sort && !head) head = s[vals[i] + 2] != s[vals[i - 1] + 2];
         }
-        flags[j] = head ? 1u : 0u;
+        const uint64_t m = ballot(head);
+        below[r] = uint32_t(popc64(m & lanemask_lt()));
+        if (lane == 0) s_cnt[r][wave] = uint32_t(popc64(m));
+        heads |= uint32_t(head) << r;
     }
+    __syncthreads();
+    // tile total and this thread's offset: all of rows before r, then the waves before in row r
+    uint32_t tile_total = 0;
+#pragma unroll
+    for (int r = 0; r < kNsItems; ++r)
+#pragma unroll
+        for (int w = 0; w < W; ++w) tile_total += s_cnt[r][w];
+    if (wave == 0) {
+        const uint64_t ex = lookback_tile<SumOp>(lbflags, int(tile), tile_total, err);
+        if (lane == 0) s_excl = uint32_t(ex);
+    }
+    __syncthreads();
+    uint32_t row_base = s_excl;
+#pragma unroll
+    for (int r = 0; r < kNsItems; ++r) {
+        uint32_t before = 0, row = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint32_t c = s_cnt[r][w];
+            if (uint32_t(w) < wave) before += c;
+            row += c;
+        }
+        const uint32_t i = base + uint32_t(r) * kD3Block;
+        if (i < n12) nm[i] = row_base + before + below[r] + ((heads >> r) & 1u);
+        row_base += row;
+    }
+    if (tid == 0 && (tile + 1) * uint64_t(kNsTile) >= n12) *total = s_excl + tile_total;
 }
 
-// Names (1-based triple ranks) into the name string, the sample order and the rank array.
-__global__ __launch_bounds__(kD3Block) void k_d3_names(const uint32_t *__restrict__ vals,
-                                                       const uint32_t *__restrict__ flags,
-                                                       const int32_t *__restrict__ excl,
-                                                       uint32_t n12, uint32_t n1,
-                                                       uint32_t *__restrict__ R,
-                                                       uint32_t *__restrict__ sa12,
-                                                       uint32_t *__restrict__ rank) {
+// Names of the sorted samples to where the next step reads them: into the name string when
+// names repeat (the recursion ranks the samples), else the ranks themselves (name = j + 1)
+// and the sample order.
+__global__ __launch_bounds__(kD3Block) void k_d3_scatter(const uint32_t *__restrict__ vals,
+                                                         const uint32_t *__restrict__ nm,
+                                                         uint32_t n12, uint32_t n1, int unique,
+                                                         uint32_t *__restrict__ R,
+                                                         uint32_t *__restrict__ sa12,
+                                                         uint32_t *__restrict__ rank) {
     for (uint32_t j = blockIdx.x * kD3Block + threadIdx.x; j < n12; j += gridDim.x * kD3Block) {
         const uint32_t p = vals[j];
-        const uint32_t name = uint32_t(excl[j]) + flags[j];
-        R[name_index(p, n1)] = name;
-        sa12[j] = p;
-        rank[p] = name;
+        if (unique) {
+            rank[p] = j + 1u;
+            sa12[j] = p;
+        } else {
+            R[name_index(p, n1)] = nm[j];
+        }
     }
 }
 
@@ -192,16 +248,22 @@ struct Rec {
     uint32_t c0, c1, r1, r2;
 };
 
+// Comparison record of every position of a level, in position order: its symbol, the next
+// symbol and the ranks one and two further.  A merge element then costs one random 16-byte
+// read instead of one for the symbols and one for the ranks.
 template <bool TOP>
-__device__ __forceinline__ Rec rec_of(const uint8_t *__restrict__ text,
-                                      const uint32_t *__restrict__ s,
-                                      const uint32_t *__restrict__ rank, uint32_t n, uint32_t x) {
-    Rec r;
-    r.c0 = sym<TOP>(text, s, n, x);
-    r.c1 = sym<TOP>(text, s, n, x + 1);
-    r.r1 = rank[x + 1];
-    r.r2 = rank[x + 2];
-    return r;
+__global__ __launch_bounds__(kD3Block) void k_d3_recs(const uint8_t *__restrict__ text,
+                                                      const uint32_t *__restrict__ s,
+                                                      const uint32_t *__restrict__ rank,
+                                                      uint32_t n, uint4 *__restrict__ rec) {
+    for (uint32_t x = blockIdx.x * kD3Block + threadIdx.x; x < n; x += gridDim.x * kD3Block)
+        rec[x] = make_uint4(sym<TOP>(text, s, n, x), sym<TOP>(text, s, n, x + 1), rank[x + 1],
+                            rank[x + 2]);
+}
+
+__device__ __forceinline__ Rec load_rec(const uint4 *__restrict__ rec, uint32_t x) {
+    const uint4 v = rec[x];
+    return Rec{v.x, v.y, v.z, v.w};
 }
 
 // Suffix a (a = 0 mod 3) before sample b?  Equal symbols 0 are separators (top level only:
@@ -217,13 +279,10 @@ __device__ __forceinline__ bool d3_less(const Rec &a, uint32_t ap, const Rec &b,
 
 // Merge-path split of every tile boundary: split[t] = how many of the first t * kMgTile
 // outputs come from A (the 0 mod 3 list).
-template <bool TOP>
-__global__ __launch_bounds__(kD3Block) void k_d3_split(const uint8_t *__restrict__ text,
-                                                       const uint32_t *__restrict__ s,
-                                                       const uint32_t *__restrict__ rank,
-                                                       uint32_t n, const uint32_t *__restrict__ A,
-                                                       uint32_t na, const uint32_t *__restrict__ B,
-                                                       uint32_t nb, uint32_t ntiles,
+__global__ __launch_bounds__(kD3Block) void k_d3_split(const uint4 *__restrict__ rec, uint32_t n,
+                                                       const uint32_t *__restrict__ A, uint32_t na,
+                                                       const uint32_t *__restrict__ B, uint32_t nb,
+                                                       uint32_t ntiles,
                                                        uint32_t *__restrict__ split) {
     for (uint32_t t = blockIdx.x * kD3Block + threadIdx.x; t <= ntiles; t += gridDim.x * kD3Block) {
         const uint64_t dd = uint64_t(t) * kMgTile;
@@ -232,10 +291,8 @@ __global__ __launch_bounds__(kD3Block) void k_d3_split(const uint8_t *__restrict
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
             const uint32_t ap = A[mid], bp = B[d - 1 - mid];
-            if (d3_less(rec_of<TOP>(text, s, rank, n, ap), ap, rec_of<TOP>(text, s, rank, n, bp), bp))
-                lo = mid + 1;
-            else
-                hi = mid;
+            if (d3_less(load_rec(rec, ap), ap, load_rec(rec, bp), bp)) lo = mid + 1;
+            else hi = mid;
         }
         split[t] = lo;
     }
@@ -244,11 +301,8 @@ __global__ __launch_bounds__(kD3Block) void k_d3_split(const uint8_t *__restrict
 // One tile of kMgTile outputs: the tile's runs of A and B with their comparison records go to
 // LDS, each thread finds its own split by merge path and merges kMgItems outputs, and the
 // tile is written out contiguously.
-template <bool TOP>
-__global__ __launch_bounds__(kD3Block) void k_d3_merge(const uint8_t *__restrict__ text,
-                                                       const uint32_t *__restrict__ s,
-                                                       const uint32_t *__restrict__ rank,
-                                                       uint32_t n, const uint32_t *__restrict__ A,
+__global__ __launch_bounds__(kD3Block) void k_d3_merge(const uint4 *__restrict__ rec, uint32_t n,
+                                                       const uint32_t *__restrict__ A,
                                                        uint32_t na_all,
                                                        const uint32_t *__restrict__ B,
                                                        uint32_t nb_all,
@@ -274,7 +328,7 @@ __global__ __launch_bounds__(kD3Block) void k_d3_merge(const uint8_t *__restrict
     for (uint32_t i = tid; i < cnt; i += kD3Block) {
         const uint32_t x = i < na ? A[a0 + i] : B[b0 + (i - na)];
         s_pos[i] = x;
-        s_rec[i] = rec_of<TOP>(text, s, rank, n, x);
+        s_rec[i] = load_rec(rec, x);
     }
     __syncthreads();
     const uint32_t k = tid * kMgItems;
@@ -326,8 +380,8 @@ struct Level {
 
 struct Layout {
     std::vector<Level> lev;
-    uint32_t *flags = nullptr;  // [n12 of the top]
-    int32_t *excl = nullptr;    // [n12 of the top]
+    uint32_t *nm = nullptr;     // [n12 of the top] names in sorted order
+    uint4 *rec = nullptr;       // [n of the top] comparison records
     uint64_t *lbflags = nullptr;
     uint32_t *tick = nullptr;
     uint32_t *state = nullptr;  // [0] error bits, [1] name count
@@ -361,9 +415,9 @@ void carve_dc3(Carver &c, int64_t n, const Tune &t, uint32_t *top_out, Layout *L
     }
     const int64_t n12 = L->lev[0].n12 > 0 ? L->lev[0].n12 : 1;
     const int64_t items = std::max<int64_t>(n12, L->lev[0].n0);
-    L->flags = c.take<uint32_t>(n12);
-    L->excl = c.take<int32_t>(n12);
-    L->lbflags = c.take<uint64_t>(scan_flags_words(n12) + 16);
+    L->nm = c.take<uint32_t>(n12);
+    L->rec = c.take<uint4>(n);
+    L->lbflags = c.take<uint64_t>(n12 / kNsTile + 16);
     L->tick = c.take<uint32_t>(64);
     L->state = c.take<uint32_t>(64);
     L->split = c.take<uint32_t>((n + kMgTile - 1) / kMgTile + 2);
@@ -428,24 +482,20 @@ struct Dc3 {
             SA_HIP(hipGetLastError());
             SA_TRY(sort(v.n12, 2 * b, cur, &cur));
         }
+        const int64_t ntiles = (v.n12 + kNsTile - 1) / kNsTile;
+        SA_TRY(launch_fill_u64(L.lbflags, ntiles, 0, st));
+        SA_TRY(launch_fill_u32(L.tick, 1, 0, st));
         {
-            TimedScope ts("dc3_names", double(v.n12) * 20.0, st);
+            // keys 8 (+ 8 for the first two names' comparison with two sorts) + names 4
+            TimedScope ts("dc3_names", double(v.n12) * (two ? 20.0 : 12.0), st);
             if (top)
-                hipLaunchKernelGGL(k_d3_heads<true>, dim3(g), dim3(kD3Block), 0, st, L.sb.keys[cur],
-                                   L.sb.vals[cur], v.s, n12, 0, L.flags);
+                hipLaunchKernelGGL(k_d3_name_scan<true>, dim3(unsigned(ntiles)), dim3(kD3Block), 0,
+                                   st, L.sb.keys[cur], L.sb.vals[cur], v.s, n12, 0, L.nm,
+                                   L.state + 1, L.lbflags, L.tick, L.state);
             else
-                hipLaunchKernelGGL(k_d3_heads<false>, dim3(g), dim3(kD3Block), 0, st,
-                                   L.sb.keys[cur], L.sb.vals[cur], v.s, n12, two ? 1 : 0, L.flags);
-            ts.finish();
-            SA_HIP(hipGetLastError());
-        }
-        SA_TRY(launch_scan_u32_i32(L.flags, L.excl, v.n12, reinterpret_cast<int32_t *>(L.state + 1),
-                                   L.lbflags, L.tick, L.state, st));
-        SA_TRY(launch_fill_u32(v.R + v.n12, 3, 0, st));
-        {
-            TimedScope ts("dc3_names", double(v.n12) * 24.0, st);
-            hipLaunchKernelGGL(k_d3_names, dim3(g), dim3(kD3Block), 0, st, L.sb.vals[cur], L.flags,
-                               L.excl, n12, uint32_t(v.n1), v.R, v.sa12, v.rank);
+                hipLaunchKernelGGL(k_d3_name_scan<false>, dim3(unsigned(ntiles)), dim3(kD3Block), 0,
+                                   st, L.sb.keys[cur], L.sb.vals[cur], v.s, n12, two ? 1 : 0, L.nm,
+                                   L.state + 1, L.lbflags, L.tick, L.state);
             ts.finish();
             SA_HIP(hipGetLastError());
         }
@@ -455,7 +505,18 @@ struct Dc3 {
                                  "sa_build_dc3: device check failed (code " + std::to_string(host[0]) + ")");
         if (host[1] < 1 || host[1] > n12) return fail(SA_ERR_HIP, "sa_build_dc3: bad name count");
         *descend = host[1] < n12;
-        if (*descend) L.lev[d + 1].K = host[1];
+        if (*descend) {
+            L.lev[d + 1].K = host[1];
+            SA_TRY(launch_fill_u32(v.R + v.n12, 3, 0, st));
+        }
+        {
+            // positions 4 + names 4 (descending) or sample order 4; one scattered word
+            TimedScope ts("dc3_names", double(v.n12) * 12.0, st);
+            hipLaunchKernelGGL(k_d3_scatter, dim3(g), dim3(kD3Block), 0, st, L.sb.vals[cur], L.nm,
+                               n12, uint32_t(v.n1), *descend ? 0 : 1, v.R, v.sa12, v.rank);
+            ts.finish();
+            SA_HIP(hipGetLastError());
+        }
         return SA_OK;
     }
 
@@ -489,31 +550,31 @@ struct Dc3 {
         SA_TRY(sort(v.n0, cb + rb, 0, &cur));
         const uint32_t *A = L.sb.vals[cur];
         const uint32_t ntiles = uint32_t((v.n + kMgTile - 1) / kMgTile);
-        // symbols (top: 1 byte, below: 4) + ranks, per comparison record
-        const double rec = top ? 10.0 : 16.0;
         {
-            TimedScope ts("dc3_merge", double(ntiles + 1) * 4.0, st);
+            // symbols (top: 1 byte each, below: 4) + ranks 8 read; a 16-byte record written
+            TimedScope ts("dc3_recs", double(v.n) * (top ? 26.0 : 32.0), st);
             if (top)
-                hipLaunchKernelGGL(k_d3_split<true>, dim3(grid_for(ntiles + 1)), dim3(kD3Block), 0,
-                                   st, text, v.s, v.rank, uint32_t(v.n), A, uint32_t(v.n0),
-                                   v.sa12, uint32_t(v.n12), ntiles, L.split);
+                hipLaunchKernelGGL(k_d3_recs<true>, dim3(grid_for(v.n)), dim3(kD3Block), 0, st,
+                                   text, v.s, v.rank, uint32_t(v.n), L.rec);
             else
-                hipLaunchKernelGGL(k_d3_split<false>, dim3(grid_for(ntiles + 1)), dim3(kD3Block), 0,
-                                   st, text, v.s, v.rank, uint32_t(v.n), A, uint32_t(v.n0),
-                                   v.sa12, uint32_t(v.n12), ntiles, L.split);
+                hipLaunchKernelGGL(k_d3_recs<false>, dim3(grid_for(v.n)), dim3(kD3Block), 0, st,
+                                   text, v.s, v.rank, uint32_t(v.n), L.rec);
             ts.finish();
             SA_HIP(hipGetLastError());
         }
         {
-            TimedScope ts("dc3_merge", double(v.n) * (8.0 + rec), st);
-            if (top)
-                hipLaunchKernelGGL(k_d3_merge<true>, dim3(ntiles), dim3(kD3Block), 0, st, text, v.s,
-                                   v.rank, uint32_t(v.n), A, uint32_t(v.n0), v.sa12,
-                                   uint32_t(v.n12), L.split, v.out, L.state);
-            else
-                hipLaunchKernelGGL(k_d3_merge<false>, dim3(ntiles), dim3(kD3Block), 0, st, text,
-                                   v.s, v.rank, uint32_t(v.n), A, uint32_t(v.n0), v.sa12,
-                                   uint32_t(v.n12), L.split, v.out, L.state);
+            TimedScope ts("dc3_merge", double(ntiles + 1) * 4.0, st);
+            hipLaunchKernelGGL(k_d3_split, dim3(grid_for(ntiles + 1)), dim3(kD3Block), 0, st, L.rec,
+                               uint32_t(v.n), A, uint32_t(v.n0), v.sa12, uint32_t(v.n12), ntiles,
+                               L.split);
+            ts.finish();
+            SA_HIP(hipGetLastError());
+        }
+        {
+            // list entry 4 + its 16-byte record + output 4
+            TimedScope ts("dc3_merge", double(v.n) * 24.0, st);
+            hipLaunchKernelGGL(k_d3_merge, dim3(ntiles), dim3(kD3Block), 0, st, L.rec, uint32_t(v.n),
+                               A, uint32_t(v.n0), v.sa12, uint32_t(v.n12), L.split, v.out, L.state);
             ts.finish();
             SA_HIP(hipGetLastError());
         }

@@ -105,9 +105,9 @@ def test_dc3_host_checks_and_workspace():
     assert _abi.sa_build_dc3_ws_bytes(0) == -1
     assert _abi.sa_build_dc3_ws_bytes(1) > 0
     big = _abi.sa_build_dc3_ws_bytes(50_100_000)
-    # per suffix: ranks, samples and name strings over the shrinking levels, plus the sort
-    # buffers for two thirds of the suffixes
-    assert 30 * 50_100_000 < big < 70 * 50_100_000
+    # per suffix: ranks, samples and name strings over the shrinking levels, the sort buffers
+    # for two thirds of the suffixes and a 16-byte comparison record
+    assert 40 * 50_100_000 < big < 80 * 50_100_000
 
 
 def test_default_tile_for_wide_digits_is_accepted():
