@@ -11,8 +11,8 @@
  *    library never allocates device memory inside these calls and never frees caller memory.
  *    Workspace contents are scratch: nothing is carried from one call to the next.
  *  - Streams: every call is ordered on `stream`.  Calls that report a count or status to the
- *    host (sa_build, sa_overlaps, sa_lookup, sa_pack, sa_sort_pairs, sa_revcomp_text,
- *    sa_strand_rows) synchronise `stream` before they return; sa_lcp does not.
+ *    host (sa_build, sa_build_dc3, sa_overlaps, sa_lookup, sa_pack, sa_sort_pairs,
+ *    sa_revcomp_text, sa_strand_rows) synchronise `stream` before they return; sa_lcp does not.
  *  - Errors: every call returns an int status (SA_OK or a negative SA_ERR_*) and never throws
  *    across the ABI.  sa_last_error() returns a message for the calling thread's last failure.
  *    On error the outputs are unspecified; inputs are never modified.
