@@ -182,6 +182,14 @@ int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa
  * default 4. */
 int sa_lcp_set_chunk(int32_t chunk);
 
+/* Size from which sa_lcp stores the scan's lengths by text position first and then gathers
+ * lcp[i] = plcp[sa[i]], instead of writing lcp[isa[p]] at random: above the last-level cache
+ * (about 64 M positions of 4-byte lengths) a random gather costs about half a random scatter.
+ * The workspace then holds n more int32 (sa_lcp_ws_bytes accounts for it).  Both forms give
+ * the same array.  min_n >= 0 sets it (process-wide; size workspaces after setting it) and
+ * returns the previous value; min_n < 0 only returns the current one (default 2^26). */
+int64_t sa_lcp_plcp_min(int64_t min_n);
+
 /* ---------------------------------------------------------------------------------------- */
 /* Pattern lookup (Sec. IV: the suffix array is searched to decide whether a string -- e.g. a  */
 /* fragment -- is a prefix of a suffix of the text).                                          */

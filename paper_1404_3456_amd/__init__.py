@@ -30,6 +30,7 @@ from ._abi import (  # noqa: F401
     sa_build_ws_bytes,
     sa_copy_u32,
     sa_lcp,
+    sa_lcp_plcp_min,
     sa_lcp_set_chunk,
     sa_lcp_ws_bytes,
     sa_lookup,

@@ -89,6 +89,7 @@ def load():
         "sa_lookup": ([P, I64, P, P, P, I64, ctypes.c_int32, P, P, I64, P], ctypes.c_int),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
         "sa_lcp_set_chunk": ([I32], ctypes.c_int),
+        "sa_lcp_plcp_min": ([I64], I64),
         "sa_overlaps_ws_bytes": ([I64, I64, I64], I64),
         "sa_overlaps": ([P, I64, P, P, P, I32, P, I64, P, P, I64, P, P], ctypes.c_int),
         "sa_timing_enable": ([I32], ctypes.c_int),
@@ -411,6 +412,12 @@ def sa_overlaps_rc(text, min_len: int, stream=None):
 
 def sa_lcp_set_chunk(chunk: int):
     _check(load().sa_lcp_set_chunk(int(chunk)))
+
+
+def sa_lcp_plcp_min(min_n: int = -1) -> int:
+    """Size from which sa_lcp gathers from a position-ordered LCP; min_n >= 0 sets it and
+    returns the previous value, min_n < 0 only reads it."""
+    return int(load().sa_lcp_plcp_min(int(min_n)))
 
 
 _ovl_ws_hint = {}

@@ -110,6 +110,18 @@ def test_dc3_host_checks_and_workspace():
     assert 40 * 50_100_000 < big < 80 * 50_100_000
 
 
+def test_lcp_plcp_setting_and_workspace():
+    default = _abi.sa_lcp_plcp_min(-1)
+    assert default == 1 << 26
+    small = _abi.sa_lcp_ws_bytes(1000)
+    assert _abi.sa_lcp_plcp_min(0) == default
+    try:
+        assert _abi.sa_lcp_ws_bytes(1000) >= small + 4000  # room for the position-ordered LCP
+    finally:
+        assert _abi.sa_lcp_plcp_min(default) == 0
+    assert _abi.sa_lcp_ws_bytes(1000) == small
+
+
 def test_default_tile_for_wide_digits_is_accepted():
     """11-bit digits with the tile left at its default resolve to a 512-thread tile (workspace
     sizing goes through the same resolution, so a size comes back instead of an error)."""

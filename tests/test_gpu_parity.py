@@ -217,6 +217,29 @@ def test_repeat_runs_identical(lib):
             assert np.array_equal(a, b)
 
 
+# ---- LCP through the position-ordered form (the one texts above 2^26 positions take) ---------
+
+def test_lcp_position_ordered_form(lib):
+    prev = lib.sa_lcp_plcp_min(0)
+    try:
+        for name in sorted(EDGE):
+            assert_parity(lib, np.frombuffer(EDGE[name], dtype=np.uint8).copy(), min_len=3,
+                          label=name)
+        assert_parity(lib, synth.random_dna_reads(11, 200, 0, 50, allow_empty=True), 4)
+        for seed in range(2):
+            t = synth.genome_reads(seed, 3000 + 1000 * seed, 300, 80 + 20 * seed, err=0.01 * seed)
+            assert_parity(lib, t, min_len=15, label=f"genome{seed}")
+        for chunk in (1, 16):
+            lib.sa_lcp_set_chunk(chunk)
+            try:
+                r = synth.small_plain()
+                assert_parity(lib, r.text, min_len=r.min_len, label=f"chunk {chunk}")
+            finally:
+                lib.sa_lcp_set_chunk(4)
+    finally:
+        lib.sa_lcp_plcp_min(prev)
+
+
 # ---- batched build: many independent texts in one set of launches ---------------------------
 
 def _batched_case(seed, n_sets, g_lo=200, g_hi=4000):
