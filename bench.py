@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
     ap.add_argument("--lcp-chunk", type=int, default=0)
+    ap.add_argument("--seg-pack", type=int, default=0,
+                    help="batched: at most this many characters per build (0: one build)")
     ap.add_argument("--sa-algo", choices=("doubling", "dc3"), default="doubling",
                     help="suffix-array construction of the timed path: prefix doubling "
                          "(sa_build) or the skew recursion (sa_build_dc3); same array")
@@ -98,8 +100,8 @@ def bench_batched(args, pkg, torch, np):
     text = torch.from_numpy(cat).cuda()
     min_len = 40
     tuning = None
-    if args.digit_bits or args.block or args.items:
-        tuning = pkg.Tuning(args.digit_bits, args.block, args.items, 0)
+    if args.digit_bits or args.block or args.items or args.seg_pack:
+        tuning = pkg.Tuning(args.digit_bits, args.block, args.items, args.seg_pack)
     tune_report = None
     if args.autotune:
         from paper_1404_3456_amd import autotune
@@ -107,6 +109,10 @@ def bench_batched(args, pkg, torch, np):
             text, off, candidates=[(8, 512, 16), (9, 512, 16), (9, 256, 16), (11, 512, 16)],
             seg_packs=(0, 1 << 28), reps=1, use_cache=False, log=log)
         log(f"autotuned: {tuning}")
+
+    plain_tuning = None
+    if tuning is not None and (tuning.digit_bits or tuning.block_threads or tuning.items_per_thread):
+        plain_tuning = pkg.Tuning(tuning.digit_bits, tuning.block_threads, tuning.items_per_thread, 0)
 
     def batched():
         sa, isa = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=args.graph)
@@ -118,7 +124,7 @@ def bench_batched(args, pkg, torch, np):
         outs = []
         for s in range(len(sets)):
             t = text[off[s]:off[s + 1]]
-            sa, isa = pkg.sa_build(t, tuning=tuning)
+            sa, isa = pkg.sa_build(t, tuning=plain_tuning)
             lcp = pkg.sa_lcp(t, sa, isa)
             outs.append(pkg.sa_overlaps(t, sa, isa, lcp, min_len))
         return outs
