@@ -107,6 +107,30 @@ def positional_overlaps(starts, read_len, min_len):
     return np.asarray(out, dtype=np.int32).reshape(-1, 3)
 
 
+def positional_overlaps_ragged(starts, lengths, min_len):
+    """Ground truth for error-free reads of any lengths cut from a random sequence: a read a
+    (covering [s_a, e_a)) overlaps b with l = e_a - s_b exactly when s_a <= s_b, e_a <= e_b
+    and l >= min_len (a's suffix and b's prefix are then the same stretch of the sequence);
+    longer chance matches are ignored, as for positional_overlaps.  Rows sorted by (a, b)."""
+    starts = np.asarray(starts, dtype=np.int64)
+    ends = starts + np.asarray(lengths, dtype=np.int64)
+    order = np.argsort(starts, kind="stable")
+    ss = starts[order]
+    lo = np.searchsorted(ss, starts, "left")
+    hi = np.searchsorted(ss, ends - min_len, "right")
+    cnt = np.maximum(hi - lo, 0)
+    total = int(cnt.sum())
+    a = np.repeat(np.arange(starts.size, dtype=np.int64), cnt)
+    first = np.repeat(lo, cnt)
+    k = np.arange(total, dtype=np.int64) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    b = order[first + k]
+    ell = ends[a] - starts[b]
+    keep = (a != b) & (ends[a] <= ends[b]) & (ell >= min_len)
+    a, b, ell = a[keep], b[keep], ell[keep]
+    o = np.lexsort((b, a))
+    return np.stack([a[o], b[o], ell[o]], axis=1).astype(np.int32)
+
+
 def reversed_reads_text(text) -> np.ndarray:
     """Same reads, each written backwards, separators in place."""
     text = np.asarray(text).copy()

@@ -189,6 +189,25 @@ def test_small_positional_ground_truth(small):
     assert np.array_equal(oracle.overlaps_brute(r.text, r.min_len), want)
 
 
+def test_ragged_positional_ground_truth():
+    """The vectorised positional truth for reads of mixed lengths (equal starts, contained
+    reads, a read ending where another ends) equals the brute-force overlaps and, for equal
+    lengths, the per-read positional truth."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([synth.SEED_BASE, 77])))
+    g = 3000
+    genome = synth.random_genome(rng, g)
+    for L_lo, L_hi in ((60, 60), (20, 90)):
+        lengths = rng.integers(L_lo, L_hi + 1, size=120)
+        starts = rng.integers(0, g - lengths + 1)
+        starts[5] = starts[6]            # equal starts
+        starts[7], lengths[7] = starts[8], lengths[8]  # identical reads
+        text = synth.layout_text(genome, starts, lengths, 0.0, None)
+        want = checks.positional_overlaps_ragged(starts, lengths, 15)
+        assert np.array_equal(oracle.overlaps_brute(text, 15), want), (L_lo, L_hi)
+        if L_lo == L_hi:
+            assert np.array_equal(checks.positional_overlaps(starts, L_lo, 15), want)
+
+
 def test_small_invariants(small):
     r, sa, lcp = small
     checks.assert_sa_basic(r.text, sa)
