@@ -113,3 +113,50 @@ def test_full_max_size(pkg):
     rows = ovl[np.sort(rng.choice(ovl.shape[0], size=2000, replace=False))]
     checks.assert_overlaps_valid(text, rows, 100)
     print(f"max-size case: {want.shape[0]} overlap rows checked", flush=True)
+
+
+def test_full_batched_256(pkg):
+    """The 256-set batched workload (1.43 G characters) in one build, as the benchmark runs it:
+    every set's block of the SA is a permutation of its own positions, ISA is the inverse, the
+    oracle's sampled adjacent order and LCP hold inside every set with LCP 0 at set starts, no
+    overlap row pairs reads of different sets, and the rows of every eighth set equal the
+    oracle's overlaps of that set alone."""
+    sets = synth.batched_sets()
+    off = np.concatenate([[0], np.cumsum([s.text.size for s in sets])]).astype(np.int64)
+    cat = np.concatenate([s.text for s in sets])
+    n = cat.size
+    print(f"full-size batched: {len(sets)} sets, n={n}", flush=True)
+    t = torch.from_numpy(cat).cuda()
+    sa, isa = pkg.sa_build_batched(t, off, use_graph=False)
+    lcp = pkg.sa_lcp(t, sa, isa)
+    ovl = pkg.sa_overlaps(t, sa, isa, lcp, 40)
+    torch.cuda.synchronize()
+    sa, isa, lcp, ovl = sa.cpu().numpy(), isa.cpu().numpy(), lcp.cpu().numpy(), ovl.cpu().numpy()
+    del t
+    assert np.all(np.bincount(sa, minlength=n) == 1), "SA is not a permutation"
+    assert np.array_equal(isa[sa], np.arange(n, dtype=np.int32))
+    del isa
+    for s in range(len(sets)):
+        lo, hi = int(off[s]), int(off[s + 1])
+        blk = sa[lo:hi]
+        assert blk.min() == lo and blk.max() == hi - 1, f"set {s} block"
+        seps = checks.separators(sets[s].text) + lo
+        assert np.array_equal(blk[: seps.size], seps), f"set {s}: separators first, in order"
+        assert lcp[lo] == 0, f"set {s} first LCP"
+    starts = set(off[:-1].tolist())
+    rng = np.random.default_rng(n)
+    idx = np.unique(rng.integers(1, n, size=400_000))
+    idx = idx[~np.isin(idx, list(starts))]
+    bad, first = oracle.check_adjacent(cat, sa, lcp, idx)
+    assert bad == 0, f"first bad adjacent pair at {first}"
+    del sa, lcp
+    reads = np.array([0] + [int((s.text == ord("$")).sum()) for s in sets]).cumsum()
+    set_of_read = np.repeat(np.arange(len(sets)), np.diff(reads))
+    assert np.array_equal(set_of_read[ovl[:, 0]], set_of_read[ovl[:, 1]]), "rows across sets"
+    for s in range(0, len(sets), 8):
+        a0, a1 = np.searchsorted(ovl[:, 0], [reads[s], reads[s + 1]])
+        want = oracle.overlaps(sets[s].text, 40).astype(np.int64)
+        want[:, :2] += reads[s]
+        assert np.array_equal(ovl[a0:a1].astype(np.int64), want), f"set {s} overlaps"
+    print(f"full-size batched: {ovl.shape[0]} rows, {len(range(0, len(sets), 8))} sets against "
+          f"the oracle", flush=True)
