@@ -132,3 +132,35 @@ def test_borrowed_texts_and_deferred_rejection(pkg):
             srv.asm_release(jid)
         srv.asm_release(bad_id)
         assert srv.asm_server_stats()["arena_used"] == 0
+
+
+def test_full_serving_jobs(pkg):
+    """The serving workload's first 64 jobs (genome 1 kbp-5 Mbp log-uniform, reads 150-800 bp,
+    8x, 0.5 % substitutions) submitted at once to a server with the benchmark's 64 GiB arena,
+    4 workers and batches of up to 64 jobs: every job against the oracle -- SA and LCP exactly
+    up to 2 M characters, by the oracle's sampled adjacent order and LCP above, and the
+    overlaps (>= 40) exactly."""
+    _, jobs = synth.serving_jobs(n_jobs=64, rate_per_s=1.0)
+    print(f"full-size serving: {len(jobs)} jobs, {sum(j.n for j in jobs)} characters", flush=True)
+    with pkg.AsmServer(64 << 30, max_jobs_per_batch=64, workers=4, mode=0) as srv:
+        ids = [srv.asm_submit(j.text, 40) for j in jobs]
+        for jid, job in zip(ids, jobs):
+            r = wait(srv, jid, timeout=300.0)
+            assert r["status"] == 0, job.name
+            sa, isa, lcp, ovl = host(r)
+            t = job.text
+            assert np.array_equal(isa[sa], np.arange(t.size)), job.name
+            if t.size <= 2_000_000:
+                want = oracle.suffix_array(t)
+                assert np.array_equal(sa, want), job.name
+                assert np.array_equal(lcp, oracle.lcp_array(t, want)), job.name
+            else:
+                assert np.all(np.bincount(sa, minlength=t.size) == 1), job.name
+                rng = np.random.default_rng(t.size)
+                idx = np.unique(rng.integers(1, t.size, size=50_000))
+                bad, first = oracle.check_adjacent(t, sa, lcp, idx)
+                assert bad == 0, (job.name, first)
+            assert np.array_equal(ovl, oracle.overlaps(t, 40)), job.name
+            srv.asm_release(jid)
+        st = srv.asm_server_stats()
+        assert st["jobs_done"] == len(jobs) and st["arena_used"] == 0
