@@ -85,8 +85,8 @@ def max_size_text():
 
 def test_full_max_size(pkg):
     """n = 2^31 - 3 (positions, ranks and counts at the edge of 32 bits): SA, ISA, LCP and
-    overlaps through the C ABI.  SA and LCP: permutation, the oracle's sampled adjacent order
-    and LCP.  Overlaps: the exact positional truth of error-free reads from a random genome,
+    overlaps through the C ABI, and the skew construction's SA.  SA and LCP: permutation, the
+    oracle's sampled adjacent order and LCP; the skew SA equal to the checked one.  Overlaps: the exact positional truth of error-free reads from a random genome,
     and direct string checks of sampled rows."""
     text, starts, lengths = max_size_text()
     n = text.size
@@ -96,12 +96,19 @@ def test_full_max_size(pkg):
     lcp = pkg.sa_lcp(t, sa, isa)
     ovl = pkg.sa_overlaps(t, sa, isa, lcp, 100)
     torch.cuda.synchronize()
-    print("max-size case: GPU done", flush=True)
+    torch.cuda.empty_cache()  # the skew build's workspace is about 72 bytes per suffix
+    sa3, _, levels = pkg.sa_build_dc3(t, isa=False, return_levels=True)
+    same_dc3 = bool(torch.equal(sa3, sa))
+    del sa3
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(f"max-size case: GPU done (skew build: {levels} levels)", flush=True)
     sa, isa, lcp, ovl = sa.cpu().numpy(), isa.cpu().numpy(), lcp.cpu().numpy(), ovl.cpu().numpy()
     del t
     checks.assert_sa_basic(text, sa)
     assert np.array_equal(isa[sa], np.arange(n, dtype=np.int32))
     del isa
+    assert same_dc3, "the skew construction differs from the doubling one"
     rng = np.random.default_rng(7)
     idx = np.unique(np.concatenate([rng.integers(1, n, size=200_000), [1, n - 1]]))
     bad, first = oracle.check_adjacent(text, sa, lcp, idx)
