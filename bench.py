@@ -89,8 +89,9 @@ def cpu_baseline(scale):
 
 
 def bench_batched(args, pkg, torch, np):
-    """256 independent fragment sets: one batched build (all sets per launch, doubling rounds
-    replayed from a hipGraph) against the plain path run set by set, same GPU, same stream."""
+    """256 independent fragment sets: one batched build (all sets per launch; doubling rounds
+    driven from the host, or replayed from a hipGraph with --graph) against the plain path run
+    set by set, same GPU, same stream."""
     from paper_1404_3456_amd import synth
     t0 = time.perf_counter()
     sets = synth.batched_sets(max_total=args.max_total or None)
