@@ -340,6 +340,7 @@ def bench_reconstruct(args, pkg, torch, np):
     least 32 apart, ~500-base pieces, ~20,000 fragments, shuffled); one step = index build on
     the GPU (pack, SA, LCP), copy to the host, and the host search through the index."""
     from paper_1404_3456_amd import synth
+    from paper_1404_3456_amd._abi import to_host
     text_h, seq, frags = synth.two_cuttings(0, 5_000_000, 500, min_gap=32)
     dev = torch.device("cuda:0")
     text = torch.from_numpy(text_h).to(dev)
@@ -350,7 +351,7 @@ def bench_reconstruct(args, pkg, torch, np):
         t0 = time.perf_counter()
         sa, isa = pkg.sa_build(text)
         lcp = pkg.sa_lcp(text, sa, isa)
-        sa_h, isa_h, lcp_h = sa.cpu().numpy(), isa.cpu().numpy(), lcp.cpu().numpy()
+        sa_h, isa_h, lcp_h = to_host(sa, isa, lcp)
         t1 = time.perf_counter()
         res = pkg.sa_reconstruct_host(text_h, sa_h, isa_h, lcp_h)
         t2 = time.perf_counter()

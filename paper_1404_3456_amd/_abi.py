@@ -363,15 +363,25 @@ def sa_reconstruct_host(text, sa, isa, lcp, max_steps: int = 10 ** 7):
     return bytes(rs[: rs_len.value]), order[:m].tolist()
 
 
+def to_host(*tensors):
+    """Device tensors to numpy arrays through pinned host buffers (one synchronisation)."""
+    torch = _torch()
+    outs = []
+    for x in tensors:
+        h = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+        h.copy_(x, non_blocking=True)
+        outs.append(h)
+    torch.cuda.synchronize()
+    return [h.numpy() for h in outs]
+
+
 def sa_reconstruct(text, max_steps: int = 10 ** 7, stream=None):
     """Builds SA, ISA and LCP of the fragment text on the GPU, then runs the host search."""
-    torch = _torch()
     t = _dev_text(text)
     sa, isa = sa_build(t, stream=stream)
     lcp = sa_lcp(t, sa, isa, stream=stream)
-    torch.cuda.synchronize()
-    return sa_reconstruct_host(t.cpu().numpy(), sa.cpu().numpy(), isa.cpu().numpy(),
-                               lcp.cpu().numpy(), max_steps)
+    t_h, sa_h, isa_h, lcp_h = to_host(t, sa, isa, lcp)
+    return sa_reconstruct_host(t_h, sa_h, isa_h, lcp_h, max_steps)
 
 
 def sa_revcomp_text(text, stream=None):
