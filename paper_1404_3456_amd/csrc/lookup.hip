@@ -4,7 +4,8 @@
 // string (a fragment, the paper's "ID matching") is a prefix of a suffix.  For a pattern P over
 // A, C, G, T the suffixes that start with P form one interval [lo, hi) of the array: lo is the
 // first index whose suffix does not sort below P, hi the first whose suffix sorts above it.
-// One thread per pattern runs the two binary searches.  Every suffix between two suffixes that
+// One thread per pattern searches for both ends of the interval together until it meets a
+// suffix that starts with P, then for each end in its half.  Every suffix between two suffixes that
 // share x bases with P shares them too, so each comparison resumes at the smaller of the
 // prefix lengths P shares with the current interval's two ends (Manber and Myers) and then
 // compares 32 bases per step from 2-bit windows; a separator ends a suffix below any base.
@@ -76,30 +77,49 @@ __global__ __launch_bounds__(256) void k_lookup(const uint4 *__restrict__ blk,
         return;
     }
     const uint32_t m = uint32_t(b - a);
-    // lo: first index whose suffix does not sort below P
-    uint32_t L = 0, R = n, lL = 0, lR = 0;
+    // Both bounds are searched together while no suffix starting with P has been met: a
+    // suffix below P moves both right, one above P moves both left.  The first suffix that
+    // starts with P (index mid) splits them: lo lies in [L, mid], hi in [mid + 1, R].  An
+    // absent pattern thus costs one search, a present one shares most of its path.  lL and
+    // lR are P's common prefixes with the suffixes just outside the current interval.
+    uint32_t L = 0, R = n, lL = 0, lR = 0, mid = 0;
+    bool met = false;
     while (L < R) {
-        const uint32_t mid = L + (R - L) / 2;
+        mid = L + (R - L) / 2;
         const uint32_t p = uint32_t(sa[mid]);
         if (p >= n) { raise_err(err, kErrRange); break; }
         uint32_t l;
         const int c = cmp_suffix(blk, ppk, uint64_t(a), m, p, lL < lR ? lL : lR, &l);
         if (c < 0) { L = mid + 1; lL = l; }
-        else { R = mid; lR = l; }
+        else if (c > 0) { R = mid; lR = l; }
+        else { met = true; break; }
     }
-    const uint32_t lo = L;
-    // hi: first index at or after lo whose suffix sorts above P
-    R = n;
-    lL = 0;
-    lR = 0;
-    while (L < R) {
-        const uint32_t mid = L + (R - L) / 2;
-        const uint32_t p = uint32_t(sa[mid]);
-        if (p >= n) { raise_err(err, kErrRange); break; }
-        uint32_t l;
-        const int c = cmp_suffix(blk, ppk, uint64_t(a), m, p, lL < lR ? lL : lR, &l);
-        if (c <= 0) { L = mid + 1; lL = l; }
-        else { R = mid; lR = l; }
+    uint32_t lo = L;
+    if (met) {
+        // lo: first index in [L, mid] whose suffix does not sort below P (mid qualifies)
+        uint32_t aL = L, aR = mid, alL = lL, alR = m;
+        while (aL < aR) {
+            const uint32_t am = aL + (aR - aL) / 2;
+            const uint32_t p = uint32_t(sa[am]);
+            if (p >= n) { raise_err(err, kErrRange); break; }
+            uint32_t l;
+            const int c = cmp_suffix(blk, ppk, uint64_t(a), m, p, alL < alR ? alL : alR, &l);
+            if (c < 0) { aL = am + 1; alL = l; }
+            else { aR = am; alR = l; }
+        }
+        lo = aL;
+        // hi: first index in [mid + 1, R] whose suffix sorts above P
+        L = mid + 1;
+        lL = m;
+        while (L < R) {
+            const uint32_t hm = L + (R - L) / 2;
+            const uint32_t p = uint32_t(sa[hm]);
+            if (p >= n) { raise_err(err, kErrRange); break; }
+            uint32_t l;
+            const int c = cmp_suffix(blk, ppk, uint64_t(a), m, p, lL < lR ? lL : lR, &l);
+            if (c <= 0) { L = hm + 1; lL = l; }
+            else { R = hm; lR = l; }
+        }
     }
     lohi[2 * i] = int32_t(lo);
     lohi[2 * i + 1] = int32_t(L);
