@@ -280,6 +280,25 @@ def test_batched_parity(lib, seed, n_sets, use_graph):
     assert np.array_equal(ovl.astype(np.int64), want)
 
 
+def test_batched_graph_repeated_with_eager_work_between(lib):
+    """The replayed-graph build, run several times with unrelated eager builds and
+    synchronisations between the runs: every run equals the host-driven build."""
+    texts, off, cat = _batched_case(5, 40)
+    t = dev(cat)
+    want, _ = lib.sa_build_batched(t, off, use_graph=False)
+    want = want.cpu().numpy()
+    other = dev(synth.genome_reads(77, 5000, 200, 100, err=0.01))
+    other_want = oracle.suffix_array(other.cpu().numpy())
+    for rep in range(4):
+        got, isa = lib.sa_build_batched(t, off, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), f"graph run {rep}"
+        assert np.array_equal(isa.cpu().numpy()[want], np.arange(cat.size)), f"graph run {rep}"
+        o, _ = lib.sa_build(other)  # eager work between the replays
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy(), other_want), f"eager run {rep}"
+
+
 def test_batched_matches_plain_per_set(lib):
     texts, off, cat = _batched_case(9, 20, 1000, 20000)
     sa_b, _ = lib.sa_build_batched(dev(cat), off)
