@@ -17,13 +17,31 @@
 // cutting that is behind (shorter cover) takes the next fragment.  Candidates are tried in
 // increasing fragment id; the first complete reconstruction is returned.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
 
 namespace saasm {
 namespace {
+
+// Runs f(lo, hi, chunk) over [0, n) split into contiguous chunks, one host thread each (at
+// most 16); chunk c covers the c-th part, so per-chunk results concatenate in index order.
+template <class F>
+int parallel_chunks(int64_t n, F f) {
+    unsigned t = std::thread::hardware_concurrency();
+    if (t < 1) t = 1;
+    if (t > 16) t = 16;
+    if (n < 65536) t = 1;
+    std::vector<std::thread> pool;
+    for (unsigned c = 1; c < t; ++c)
+        pool.emplace_back(f, n * c / t, n * (c + 1) / t, int(c));
+    f(int64_t(0), n / t, 0);
+    for (auto &th : pool) th.join();
+    return int(t);
+}
 
 struct Recon {
     const uint8_t *t;
@@ -95,24 +113,32 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
     R.sa = sa_h;
     R.isa = isa_h;
     R.lcp = lcp_h;
-    R.frag_at.assign(size_t(n), -1);
-    int64_t s0 = 0;
-    for (int64_t p = 0; p < n; ++p) {
-        if (text_h[p] == '$') {
-            if (p == s0) return fail(SA_ERR_INVALID, "sa_reconstruct: empty fragment");
-            R.frag_at[size_t(s0)] = int32_t(R.start.size());
-            R.start.push_back(s0);
-            R.len.push_back(p - s0);
-            s0 = p + 1;
-        }
+    R.frag_at.resize(size_t(n));
+    parallel_chunks(n, [&](int64_t lo, int64_t hi, int) {
+        std::fill(R.frag_at.begin() + lo, R.frag_at.begin() + hi, -1);
+    });
+    for (int64_t s0 = 0; s0 < n;) {  // fragment by fragment: the next separator after s0
+        const void *q = memchr(text_h + s0, '$', size_t(n - s0));
+        const int64_t p = static_cast<const uint8_t *>(q) - text_h;  // text_h[n-1] is '$'
+        if (p == s0) return fail(SA_ERR_INVALID, "sa_reconstruct: empty fragment");
+        R.frag_at[size_t(s0)] = int32_t(R.start.size());
+        R.start.push_back(s0);
+        R.len.push_back(p - s0);
+        s0 = p + 1;
     }
     const int64_t m = int64_t(R.start.size());
     if (m < 2) return fail(SA_ERR_INVALID, "sa_reconstruct: need at least two fragments");
     R.min_len = *std::min_element(R.len.begin(), R.len.end());
     R.used.assign(size_t(m), 0);
-    for (int64_t i = 0; i < n; ++i)
-        if (sa_h[i] < 0 || sa_h[i] >= n || isa_h[sa_h[i]] != i)
-            return fail(SA_ERR_INVALID, "sa_reconstruct: sa/isa are not inverse permutations");
+    std::atomic<bool> bad{false};
+    parallel_chunks(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i)
+            if (sa_h[i] < 0 || sa_h[i] >= n || isa_h[sa_h[i]] != i) {
+                bad.store(true, std::memory_order_relaxed);
+                return;
+            }
+    });
+    if (bad.load()) return fail(SA_ERR_INVALID, "sa_reconstruct: sa/isa are not inverse permutations");
 
     std::vector<uint8_t> rs;      // the sequence so far
     std::vector<int32_t> order;   // fragments in placement order
@@ -151,12 +177,19 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
     // pair), by b then a in increasing id.
     std::vector<std::pair<int32_t, int32_t>> firs;
     {
-        std::vector<int32_t> c;
-        for (int32_t b = 0; b < m; ++b) {
-            R.candidates(R.start[size_t(b)], R.len[size_t(b)], m == 2, c);
-            for (int32_t a : c)
-                if (a != b && (R.len[size_t(a)] < R.len[size_t(b)] || m == 2)) firs.push_back({b, a});
-        }
+        // independent read-only walks, one chunk of fragments per host thread
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> part(16);
+        parallel_chunks(m, [&](int64_t lo, int64_t hi, int chunk) {
+            std::vector<int32_t> c;
+            for (int64_t bb = lo; bb < hi; ++bb) {
+                const int32_t b = int32_t(bb);
+                R.candidates(R.start[size_t(b)], R.len[size_t(b)], m == 2, c);
+                for (int32_t a : c)
+                    if (a != b && (R.len[size_t(a)] < R.len[size_t(b)] || m == 2))
+                        part[size_t(chunk)].push_back({b, a});
+            }
+        });
+        for (auto &pv : part) firs.insert(firs.end(), pv.begin(), pv.end());
     }
     for (const auto &fa : firs) {
         const int32_t b = fa.first, a = fa.second;
