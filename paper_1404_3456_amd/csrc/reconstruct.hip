@@ -29,18 +29,38 @@ namespace {
 
 // Runs f(lo, hi, chunk) over [0, n) split into contiguous chunks, one host thread each (at
 // most 16); chunk c covers the c-th part, so per-chunk results concatenate in index order.
+// A chunk whose thread cannot be started runs on the calling thread.  Returns false when a
+// chunk failed (an allocation inside it threw); nothing escapes a thread.
 template <class F>
-int parallel_chunks(int64_t n, F f) {
+bool parallel_chunks(int64_t n, F f) {
     unsigned t = std::thread::hardware_concurrency();
     if (t < 1) t = 1;
     if (t > 16) t = 16;
     if (n < 65536) t = 1;
+    std::atomic<bool> failed{false};
+    auto run = [&](int64_t lo, int64_t hi, int c) {
+        try {
+            f(lo, hi, c);
+        } catch (...) {
+            failed.store(true);
+        }
+    };
     std::vector<std::thread> pool;
-    for (unsigned c = 1; c < t; ++c)
-        pool.emplace_back(f, n * c / t, n * (c + 1) / t, int(c));
-    f(int64_t(0), n / t, 0);
+    try {
+        pool.reserve(t);
+    } catch (...) {
+        t = 1;
+    }
+    for (unsigned c = 1; c < t; ++c) {
+        try {
+            pool.emplace_back(run, n * c / t, n * (c + 1) / t, int(c));
+        } catch (...) {
+            run(n * c / t, n * (c + 1) / t, int(c));
+        }
+    }
+    run(int64_t(0), n / t, 0);
     for (auto &th : pool) th.join();
-    return int(t);
+    return !failed.load();
 }
 
 struct Recon {
@@ -99,10 +119,9 @@ struct Frame {
 
 using namespace saasm;
 
-extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *sa_h,
-                              const int32_t *isa_h, const int32_t *lcp_h, int32_t *order_h,
-                              uint8_t *rs_h, int64_t rs_cap, int64_t *rs_len_h,
-                              int64_t max_steps) {
+static int reconstruct_impl(const uint8_t *text_h, int64_t n, const int32_t *sa_h,
+                            const int32_t *isa_h, const int32_t *lcp_h, int32_t *order_h,
+                            uint8_t *rs_h, int64_t rs_cap, int64_t *rs_len_h, int64_t max_steps) {
     if (!text_h || !sa_h || !isa_h || !lcp_h || !order_h || !rs_len_h)
         return fail(SA_ERR_INVALID, "sa_reconstruct: NULL pointer");
     if (n < 1 || text_h[n - 1] != '$') return fail(SA_ERR_INVALID, "sa_reconstruct: text must end with '$'");
@@ -114,9 +133,10 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
     R.isa = isa_h;
     R.lcp = lcp_h;
     R.frag_at.resize(size_t(n));
-    parallel_chunks(n, [&](int64_t lo, int64_t hi, int) {
-        std::fill(R.frag_at.begin() + lo, R.frag_at.begin() + hi, -1);
-    });
+    if (!parallel_chunks(n, [&](int64_t lo, int64_t hi, int) {
+            std::fill(R.frag_at.begin() + lo, R.frag_at.begin() + hi, -1);
+        }))
+        return fail(SA_ERR_NOMEM, "sa_reconstruct: host thread failed");
     for (int64_t s0 = 0; s0 < n;) {  // fragment by fragment: the next separator after s0
         const void *q = memchr(text_h + s0, '$', size_t(n - s0));
         const int64_t p = static_cast<const uint8_t *>(q) - text_h;  // text_h[n-1] is '$'
@@ -131,13 +151,14 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
     R.min_len = *std::min_element(R.len.begin(), R.len.end());
     R.used.assign(size_t(m), 0);
     std::atomic<bool> bad{false};
-    parallel_chunks(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t i = lo; i < hi; ++i)
-            if (sa_h[i] < 0 || sa_h[i] >= n || isa_h[sa_h[i]] != i) {
-                bad.store(true, std::memory_order_relaxed);
-                return;
-            }
-    });
+    if (!parallel_chunks(n, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t i = lo; i < hi; ++i)
+                if (sa_h[i] < 0 || sa_h[i] >= n || isa_h[sa_h[i]] != i) {
+                    bad.store(true, std::memory_order_relaxed);
+                    return;
+                }
+        }))
+        return fail(SA_ERR_NOMEM, "sa_reconstruct: host thread failed");
     if (bad.load()) return fail(SA_ERR_INVALID, "sa_reconstruct: sa/isa are not inverse permutations");
 
     std::vector<uint8_t> rs;      // the sequence so far
@@ -179,7 +200,7 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
     {
         // independent read-only walks, one chunk of fragments per host thread
         std::vector<std::vector<std::pair<int32_t, int32_t>>> part(16);
-        parallel_chunks(m, [&](int64_t lo, int64_t hi, int chunk) {
+        const bool ok = parallel_chunks(m, [&](int64_t lo, int64_t hi, int chunk) {
             std::vector<int32_t> c;
             for (int64_t bb = lo; bb < hi; ++bb) {
                 const int32_t b = int32_t(bb);
@@ -189,6 +210,7 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
                         part[size_t(chunk)].push_back({b, a});
             }
         });
+        if (!ok) return fail(SA_ERR_NOMEM, "sa_reconstruct: out of host memory");
         for (auto &pv : part) firs.insert(firs.end(), pv.begin(), pv.end());
     }
     for (const auto &fa : firs) {
@@ -233,4 +255,16 @@ extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *s
         }
     }
     return fail(SA_ERR_NOTFOUND, "sa_reconstruct: no reconstruction from two cuttings");
+}
+
+extern "C" int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *sa_h,
+                              const int32_t *isa_h, const int32_t *lcp_h, int32_t *order_h,
+                              uint8_t *rs_h, int64_t rs_cap, int64_t *rs_len_h,
+                              int64_t max_steps) {
+    try {  // host allocations may throw; nothing crosses the C interface
+        return reconstruct_impl(text_h, n, sa_h, isa_h, lcp_h, order_h, rs_h, rs_cap, rs_len_h,
+                                max_steps);
+    } catch (...) {
+        return fail(SA_ERR_NOMEM, "sa_reconstruct: out of host memory");
+    }
 }
