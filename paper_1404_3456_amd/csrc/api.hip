@@ -180,7 +180,7 @@ extern "C" int sa_timing_reset(void) {
     return SA_OK;
 }
 
-extern "C" int sa_timing_get(const char *key, int64_t *launches_h, double *total_ms_h,
+static int sa_timing_get_impl(const char *key, int64_t *launches_h, double *total_ms_h,
                              double *bytes_h) {
     if (!key) return fail(SA_ERR_INVALID, "sa_timing_get: NULL key");
     timing_flush();
@@ -196,4 +196,10 @@ extern "C" int sa_timing_get(const char *key, int64_t *launches_h, double *total
     if (total_ms_h) *total_ms_h = it->second.ms;
     if (bytes_h) *bytes_h = it->second.bytes;
     return SA_OK;
+}
+
+// ---- C entry points: bodies above, host exceptions turned into statuses ------------------
+extern "C" int sa_timing_get(const char *key, int64_t *launches_h, double *total_ms_h,
+                             double *bytes_h) {
+    return guard<int>([&] { return sa_timing_get_impl(key, launches_h, total_ms_h, bytes_h); });
 }

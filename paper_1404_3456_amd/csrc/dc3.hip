@@ -624,7 +624,7 @@ extern "C" int64_t sa_build_dc3_ws_bytes(int64_t n, const sa_tuning *tune) {
     return c.off + 256;
 }
 
-extern "C" int sa_build_dc3(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
+static int sa_build_dc3_impl(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
                             void *ws, int64_t ws_bytes, const sa_tuning *tune, int32_t *levels_h,
                             hipStream_t stream) {
     if (!text || !sa || !ws) return fail(SA_ERR_INVALID, "sa_build_dc3: NULL pointer");
@@ -647,4 +647,11 @@ extern "C" int sa_build_dc3(const uint8_t *text, int64_t n, int32_t *sa, int32_t
         SA_HIP(hipGetLastError());
     }
     return SA_OK;
+}
+
+// ---- C entry points: bodies above, host exceptions turned into statuses ------------------
+extern "C" int sa_build_dc3(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
+                            void *ws, int64_t ws_bytes, const sa_tuning *tune, int32_t *levels_h,
+                            hipStream_t stream) {
+    return guard<int>([&] { return sa_build_dc3_impl(text, n, sa, isa_or_null, ws, ws_bytes, tune, levels_h, stream); });
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
 #include <string>
 
 #include "../../include/saasm.h"
@@ -19,6 +20,22 @@ int fail(int code, const std::string &msg);
         if (e_ != hipSuccess)                                                            \
             return ::saasm::fail(SA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// Runs an entry point's body; a host exception (an allocation that fails, a thread that cannot
+// start) becomes an error status instead of crossing the C interface.  The messages are short
+// enough to need no allocation themselves.
+template <class R, class F>
+R guard(F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        set_error("host alloc fail");
+        return R(SA_ERR_NOMEM);
+    } catch (...) {
+        set_error("host failure");
+        return R(SA_ERR_HIP);
+    }
+}
 
 #define SA_TRY(expr)                 \
     do {                             \

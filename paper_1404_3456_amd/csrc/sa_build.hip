@@ -493,7 +493,7 @@ extern "C" int64_t sa_build_ws_bytes(int64_t n, const sa_tuning *tune) {
     return c.off + 256;
 }
 
-extern "C" int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
+static int sa_build_impl(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
                         void *ws, int64_t ws_bytes, const sa_tuning *tune, int32_t *rounds_h,
                         hipStream_t stream) {
     if (!text || !sa || !ws) return fail(SA_ERR_INVALID, "sa_build: NULL pointer");
@@ -556,7 +556,7 @@ extern "C" int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const in
     return need + 256;
 }
 
-extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h,
+static int sa_build_batched_impl(const uint8_t *text, int64_t n, const int64_t *set_off_h,
                                 int32_t n_sets, int32_t *sa, int32_t *isa_or_null, void *ws,
                                 int64_t ws_bytes, const sa_tuning *tune, int32_t use_graph,
                                 int32_t *rounds_h, hipStream_t stream) {
@@ -595,4 +595,18 @@ extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *s
     }
     if (rounds_h) *rounds_h = rounds_max;
     return SA_OK;
+}
+
+// ---- C entry points: bodies above, host exceptions turned into statuses ------------------
+extern "C" int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_null,
+                        void *ws, int64_t ws_bytes, const sa_tuning *tune, int32_t *rounds_h,
+                        hipStream_t stream) {
+    return guard<int>([&] { return sa_build_impl(text, n, sa, isa_or_null, ws, ws_bytes, tune, rounds_h, stream); });
+}
+
+extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h,
+                                int32_t n_sets, int32_t *sa, int32_t *isa_or_null, void *ws,
+                                int64_t ws_bytes, const sa_tuning *tune, int32_t use_graph,
+                                int32_t *rounds_h, hipStream_t stream) {
+    return guard<int>([&] { return sa_build_batched_impl(text, n, set_off_h, n_sets, sa, isa_or_null, ws, ws_bytes, tune, use_graph, rounds_h, stream); });
 }

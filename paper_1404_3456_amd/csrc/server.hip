@@ -443,7 +443,7 @@ static void release_job_locked(asm_server *S, Job *j) {
 
 using namespace saasm;
 
-extern "C" int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_jobs_per_batch,
+static int asm_server_create_impl(void *arena, int64_t arena_bytes, int32_t max_jobs_per_batch,
                                  int32_t workers, int32_t mode, asm_server **out) {
     if (!arena || !out || arena_bytes < (int64_t(1) << 20) || workers < 1 || workers > 16 ||
         max_jobs_per_batch < 1 || (mode != 0 && mode != 1))
@@ -460,7 +460,7 @@ extern "C" int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_j
     return SA_OK;
 }
 
-extern "C" int asm_submit(asm_server *S, const uint8_t *text_h, int64_t n, int32_t min_len,
+static int asm_submit_impl(asm_server *S, const uint8_t *text_h, int64_t n, int32_t min_len,
                           int32_t flags, uint64_t *job_id_h) {
     if (!S || !text_h || !job_id_h) return fail(SA_ERR_INVALID, "asm_submit: NULL pointer");
     if (n < 1 || min_len < 1) return fail(SA_ERR_INVALID, "asm_submit: need n >= 1, min_len >= 1");
@@ -496,7 +496,7 @@ extern "C" int asm_submit(asm_server *S, const uint8_t *text_h, int64_t n, int32
     return SA_OK;
 }
 
-extern "C" int asm_poll(asm_server *S, uint64_t job_id, asm_result *res) {
+static int asm_poll_impl(asm_server *S, uint64_t job_id, asm_result *res) {
     if (!S || !res) return fail(SA_ERR_INVALID, "asm_poll: NULL pointer");
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->jobs.find(job_id);
@@ -521,7 +521,7 @@ extern "C" int asm_poll(asm_server *S, uint64_t job_id, asm_result *res) {
     return j->status == SA_PENDING ? SA_PENDING : SA_OK;
 }
 
-extern "C" int asm_release(asm_server *S, uint64_t job_id) {
+static int asm_release_impl(asm_server *S, uint64_t job_id) {
     if (!S) return fail(SA_ERR_INVALID, "asm_release: NULL server");
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->jobs.find(job_id);
@@ -535,7 +535,7 @@ extern "C" int asm_release(asm_server *S, uint64_t job_id) {
     return SA_OK;
 }
 
-extern "C" int asm_server_stats(asm_server *S, int64_t *out_h /* [6] */) {
+static int asm_server_stats_impl(asm_server *S, int64_t *out_h /* [6] */) {
     if (!S || !out_h) return fail(SA_ERR_INVALID, "asm_server_stats: NULL pointer");
     std::lock_guard<std::mutex> lk(S->mu);
     out_h[0] = S->batches;
@@ -547,14 +547,14 @@ extern "C" int asm_server_stats(asm_server *S, int64_t *out_h /* [6] */) {
     return SA_OK;
 }
 
-extern "C" int asm_server_fail_alloc_after(asm_server *S, int32_t k) {
+static int asm_server_fail_alloc_after_impl(asm_server *S, int32_t k) {
     if (!S || k < 0) return fail(SA_ERR_INVALID, "asm_server_fail_alloc_after: bad arguments");
     std::lock_guard<std::mutex> lk(S->mu);
     S->arena.fail_after(k);
     return SA_OK;
 }
 
-extern "C" int asm_server_destroy(asm_server *S) {
+static int asm_server_destroy_impl(asm_server *S) {
     if (!S) return fail(SA_ERR_INVALID, "asm_server_destroy: NULL server");
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -565,4 +565,35 @@ extern "C" int asm_server_destroy(asm_server *S) {
     for (auto &kv : S->jobs) delete kv.second;
     delete S;
     return SA_OK;
+}
+
+// ---- C entry points: bodies above, host exceptions turned into statuses ------------------
+extern "C" int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_jobs_per_batch,
+                                 int32_t workers, int32_t mode, asm_server **out) {
+    return guard<int>([&] { return asm_server_create_impl(arena, arena_bytes, max_jobs_per_batch, workers, mode, out); });
+}
+
+extern "C" int asm_submit(asm_server *S, const uint8_t *text_h, int64_t n, int32_t min_len,
+                          int32_t flags, uint64_t *job_id_h) {
+    return guard<int>([&] { return asm_submit_impl(S, text_h, n, min_len, flags, job_id_h); });
+}
+
+extern "C" int asm_poll(asm_server *S, uint64_t job_id, asm_result *res) {
+    return guard<int>([&] { return asm_poll_impl(S, job_id, res); });
+}
+
+extern "C" int asm_release(asm_server *S, uint64_t job_id) {
+    return guard<int>([&] { return asm_release_impl(S, job_id); });
+}
+
+extern "C" int asm_server_stats(asm_server *S, int64_t *out_h /* [6] */) {
+    return guard<int>([&] { return asm_server_stats_impl(S, out_h); });
+}
+
+extern "C" int asm_server_fail_alloc_after(asm_server *S, int32_t k) {
+    return guard<int>([&] { return asm_server_fail_alloc_after_impl(S, k); });
+}
+
+extern "C" int asm_server_destroy(asm_server *S) {
+    return guard<int>([&] { return asm_server_destroy_impl(S); });
 }
