@@ -115,6 +115,8 @@ int sa_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int
 
 /* ---------------------------------------------------------------------------------------- */
 /* Suffix array (Sec. IV), by prefix doubling over LSD radix sorts of rank-pair keys.          */
+/* A doubling round whose groups all have at most 32 members orders each group in on-chip    */
+/* memory instead of running radix passes over all its keys; the result is the same.         */
 /* ---------------------------------------------------------------------------------------- */
 
 /* Workspace bytes for sa_build on a text of n bytes. */

@@ -51,6 +51,7 @@ struct Pending {
     double bytes;
     double per_item;
     int64_t tag;  // -1: bytes final; else waiting for timing_round_items
+    int mode;     // kModeAny, or the round sort mode these bytes belong to
 };
 std::atomic<int64_t> g_next_tag{1};
 thread_local int64_t t_tag = -1;
@@ -73,6 +74,9 @@ hipEvent_t get_event() {
 }  // namespace
 
 static thread_local bool t_pause = false;
+static thread_local int t_mode = kModeAny;
+
+void timing_scope_mode(int mode) { t_mode = mode; }
 
 bool timing_on() { return g_on && !t_pause; }
 
@@ -92,6 +96,7 @@ TimedScope::TimedScope(const char *k, double fixed_bytes, double per_item_bytes,
     : TimedScope(k, fixed_bytes, s) {
     per_item = per_item_bytes;
     tag = t_tag;
+    mode = t_mode;
 }
 
 void TimedScope::finish() {
@@ -104,7 +109,7 @@ void TimedScope::finish() {
         start = nullptr;
         return;
     }
-    g_pending.push_back(Pending{start, end, key, bytes, per_item, tag});
+    g_pending.push_back(Pending{start, end, key, bytes, per_item, tag, mode});
     start = nullptr;
 }
 
@@ -113,12 +118,14 @@ int64_t timing_round_begin() {
     return t_tag;
 }
 
-void timing_round_items(int64_t tag, int64_t items) {
+void timing_round_items(int64_t tag, int64_t items, int mode) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &p : g_pending) {
         if (p.tag != tag) continue;
-        // an empty round still launched its kernels (they exit at once): timed, no bytes
-        p.bytes = items <= 0 ? 0.0 : p.bytes + p.per_item * double(items);
+        // an empty round still launched its kernels (they exit at once): timed, no bytes; so
+        // are the kernels of the sort mode the round did not use
+        const bool used = p.mode == kModeAny || p.mode == mode;
+        p.bytes = items <= 0 || !used ? 0.0 : p.bytes + p.per_item * double(items);
         p.tag = -1;
     }
 }

@@ -85,6 +85,7 @@ struct TimedScope {
     double bytes;
     double per_item = 0.0;
     int64_t tag = -1;
+    int mode = 0;
     hipStream_t stream;
     hipEvent_t start = nullptr;
     TimedScope(const char *k, double b, hipStream_t s);
@@ -92,7 +93,12 @@ struct TimedScope {
     void finish();
 };
 int64_t timing_round_begin();                       // new tag for the calling thread's round
-void timing_round_items(int64_t tag, int64_t items);  // item count of that round (0: no bytes)
+// item count of that round (0: no bytes) and how it sorted (kModeRadix or kModeRuns)
+void timing_round_items(int64_t tag, int64_t items, int mode);
+constexpr int kModeAny = 0, kModeRadix = 1, kModeRuns = 2;
+// Scopes opened by the calling thread from now on only take their round's bytes when the
+// round sorted in this mode (kModeAny: always).
+void timing_scope_mode(int mode);
 void timing_flush();  // resolve pending events (waits for them)
 void timing_poll();   // resolve only the pending events that have already completed
 void timing_pause(bool on);  // calling thread: no events while a stream is being captured
@@ -152,12 +158,18 @@ constexpr int kStKeys = 2;     // keys written by the round's key build (== kStA
 constexpr int kStH = 3;        // prefix length the groups are sorted by
 constexpr int kStRounds = 4;   // rounds completed
 constexpr int kStNext = 5;     // active count produced by the round's rank update
+constexpr int kStBig = 6;      // 1: some group entering the round has more than kRunMax members
+constexpr int kStRadixN = 7;   // items the round sorts by radix passes (kStActive or 0)
+constexpr int kStBigNext = 8;  // set by the rank update for the next round
+constexpr int kStRunsN = 9;    // items the round sorts run by run in LDS (kStActive or 0)
+constexpr int kRunMax = 32;    // largest group the run sort handles
 
 // key builders (fused with the histogram of the sort that follows)
 int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int h0,
                 const int64_t *set_off_dev, int n_sets, int key_bits, const SortBufs &b, int cur,
                 const Tune &t, hipStream_t s, int *nparts);
-int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, const SortBufs &b, int cur,
+int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, int count_word,
+                         const SortBufs &b, int cur,
                          uint64_t *lbflags, uint32_t *ticket, uint32_t *state, const Tune &t,
                          hipStream_t s, int *nparts);
 

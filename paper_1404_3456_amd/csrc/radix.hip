@@ -566,8 +566,9 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
 // rank holds group labels (the suffix-array index of the group's first member) with kDone set
 // on singletons.  A suffix still in a non-singleton group after a round with prefix length h
 // has at least h symbols before its separator, so p + h stays inside the text.  The round's
-// active count and h are read from device memory (state[kStActive], state[kStH]); the number
-// of keys written goes to state[kStKeys].
+// active count and h are read from device memory (state[count_word], state[kStH]); the number
+// of keys written goes to state[kStKeys].  A count of 0 makes the launch a no-op (its zero
+// histograms are still written).
 constexpr int kKbBlock = 512;
 constexpr int kKbItems = 8;
 constexpr int kKbTile = kKbBlock * kKbItems;
@@ -579,7 +580,8 @@ __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restric
                                                        uint32_t *__restrict__ vals, int passes,
                                                        uint32_t *__restrict__ hist,
                                                        uint64_t *lbflags, uint32_t *tick,
-                                                       uint32_t *state, uint32_t *err) {
+                                                       uint32_t *state, int count_word,
+                                                       uint32_t *err) {
     constexpr int R = 1 << D;
     constexpr int W = kKbBlock / kWave;
     extern __shared__ uint32_t s_h[];
@@ -588,7 +590,7 @@ __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restric
     __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint64_t rmask = (uint64_t(1) << rbits) - 1;
-    const uint32_t active = state[kStActive];
+    const uint32_t active = state[count_word];
     const uint32_t h = state[kStH];
     const uint32_t ntiles = active ? (n + kKbTile - 1) / kKbTile : 0u;
     for (int i = tid; i < passes * R; i += kKbBlock) s_h[i] = 0;
@@ -649,8 +651,8 @@ __global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restric
     hist_flush<D>(s_h, hist, passes);
 }
 
-int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, const SortBufs &b, int cur,
-                         uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
+int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, int count_word,
+                         const SortBufs &b, int cur, uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
                          hipStream_t s, int *nparts) {
     const int bits = 2 * rbits;
     const int P = sort_passes(bits, t);
@@ -671,10 +673,10 @@ int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, const SortB
     // every position's label is read; each active one adds rank[p+h] and its key and value
     TimedScope ts("keybuild", double(n) * 4.0, 16.0, s);
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
-        case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
-        case 9: hipLaunchKernelGGL(k_keys_dbl<9>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
-        case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, b.err); break;
+        case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
+        case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
+        case 9: hipLaunchKernelGGL(k_keys_dbl<9>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
+        case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
     ts.finish();

@@ -46,13 +46,16 @@ constexpr int kRuTile = kRuBlock * kRuItems;
 // state[kStNext].
 // In a doubling round the key's upper half is the item's previous label, so rank[V[i]] is
 // only rewritten when the label changes or the item becomes a singleton.
+// Beside each compacted slot it writes the item's text position to P_new, with bit 31 set on
+// the first member of each group, so the next round can find its groups as runs in this
+// order; and it sets state[kStBigNext] when some group has more than kRunMax members.
 // One tile per workgroup (tiles by ticket); the grid covers an upper bound on A and surplus
 // workgroups return at once.
 __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     const uint64_t *__restrict__ K, const uint32_t *__restrict__ V, const uint32_t *__restrict__ S,
     uint32_t n, int round0, uint32_t h0, int rbits, int32_t *__restrict__ sa,
-    uint32_t *__restrict__ rank, uint32_t *__restrict__ S_new, uint64_t *lbflags, uint32_t *tick,
-    uint32_t *state, uint32_t *err) {
+    uint32_t *__restrict__ rank, uint32_t *__restrict__ S_new, uint32_t *__restrict__ P_new,
+    uint64_t *lbflags, uint32_t *tick, uint32_t *state, uint32_t *err) {
     // Global memory is only touched in wave-contiguous (striped) order; the per-item logic
     // works on blocked runs of kRuItems consecutive items held in LDS.
     __shared__ uint64_t s_k[kRuTile + 2];  // keys, one neighbour each side; then the outputs
@@ -144,7 +147,10 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
             }
             const bool same = !round0 && uint32_t((s_k[1 + li] >> rbits) & lmask) == label;
             if (single || !same) lab_w[j] = label | (single ? kDone : 0u);
-            if (!single) out_w[j] = out++;
+            if (!single) {
+                out_w[j] = out++ | (head[j] ? kDone : 0u);  // bit 31: first of its group
+                if (i - g == uint32_t(kRunMax)) state[kStBigNext] = 1u;
+            }
         }
     }
     __syncthreads();  // every read of the keys is done: their storage now holds the outputs
@@ -166,7 +172,10 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
             if (lw & kDone) sa[slot] = int32_t(v);  // final; slots still in a group are rewritten later
         }
         const uint32_t o = s_out[i];
-        if (o != kNone) S_new[o] = slot;
+        if (o != kNone) {
+            S_new[o & kRankMask] = slot;
+            P_new[o & kRankMask] = v | (o & kDone);
+        }
     }
 }
 
@@ -177,7 +186,14 @@ __global__ void k_round_end(uint32_t *state, uint32_t h_first) {
     const uint32_t rounds = state[kStRounds];
     state[kStH] = rounds == 0 ? h_first : state[kStH] * 2u;
     state[kStRounds] = rounds + 1;
-    state[kStActive] = state[kStNext];
+    const uint32_t a = state[kStNext];
+    state[kStActive] = a;
+    // the next round sorts by radix passes only if a group is too large for the run sort
+    const uint32_t big = state[kStBigNext];
+    state[kStBigNext] = 0;
+    state[kStBig] = big;
+    state[kStRadixN] = big ? a : 0u;
+    state[kStRunsN] = big ? 0u : a;
 }
 
 // Adds a block's offset to suffix-array and inverse entries built for that block alone.
@@ -212,6 +228,7 @@ struct BuildLayout {
     uint32_t *packed, *sepmask, *wordcnt;
     uint32_t *rank;        // used when the caller gives no isa buffer
     uint32_t *slots[2];
+    uint32_t *pos;         // active text positions in the last round's order (bit 31: run start)
     SortBufs sb;
     uint64_t *lbflags;
     uint32_t *tickets;
@@ -227,6 +244,7 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
     L->rank = c.take<uint32_t>(n);
     L->slots[0] = c.take<uint32_t>(n);
     L->slots[1] = c.take<uint32_t>(n);
+    L->pos = c.take<uint32_t>(n);
     carve_sort(c, n, bits, t, &L->sb, true);
     const int64_t lbw = (n + kRuTile - 1) / kRuTile + (n + 2047) / 2048 + 16;
     L->lbflags = c.take<uint64_t>(lbw);
@@ -235,21 +253,108 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
     L->set_off = c.take<int64_t>(n_sets + 1);
 }
 
+// Keys of a doubling round built in the previous round's sorted order, sorted group by group
+// without radix passes.  The previous rank update left the active items in that order: slots
+// S[0..A), text positions P[0..A) with bit 31 on the first member of each group, so each group
+// is a run of at most kRunMax items (the round runs this only when state[kStBig] is 0).  Its
+// label is the slot of the run's first member.  Item o gets
+//   key = (label << rbits) | rank[p + h],
+// and goes to the run's first index plus the number of run members with a smaller key (equal
+// keys keep their order), which is where a stable sort of the whole array puts it.
+// Tiles of kKrTile items, loaded with kRunMax items of context on either side, so every run
+// that meets the tile lies inside the loaded range.  The active count and h come from
+// state[count_word] and state[kStH]; a count of 0 makes the launch a no-op.  A run longer
+// than kRunMax raises kErrRange.
+constexpr int kKrBlock = 256;
+constexpr int kKrTile = 2048;
+constexpr int kKrSpan = kKrTile + 2 * kRunMax;
+
+__global__ __launch_bounds__(kKrBlock) void k_keys_runs(
+    const uint32_t *__restrict__ P, const uint32_t *__restrict__ S,
+    const uint32_t *__restrict__ rank, uint32_t n, int rbits, const uint32_t *state,
+    int count_word, uint64_t *__restrict__ K, uint32_t *__restrict__ V, uint32_t *err) {
+    __shared__ uint32_t s_p[kKrSpan];   // position | first-of-run bit; outside [0, A): the bit alone
+    __shared__ uint32_t s_r2[kKrSpan];  // rank[p + h]
+    __shared__ uint32_t s_lab[kKrSpan]; // slot (the label, on a run's first member)
+    const uint32_t A = state[count_word];
+    const uint32_t h = state[kStH];
+    const int64_t tbase = int64_t(blockIdx.x) * kKrTile;
+    if (tbase >= int64_t(A)) return;
+    const int64_t lo = tbase - kRunMax;
+    for (int x = threadIdx.x; x < kKrSpan; x += kKrBlock) {
+        const int64_t gi = lo + x;
+        uint32_t pv = kDone, r2 = 0, lab = 0;
+        if (gi >= 0 && gi < int64_t(A)) {
+            pv = P[gi];
+            lab = S[gi];
+            const uint32_t p = pv & kRankMask;
+            if (p < n && h < n - p) r2 = rank[p + h] & kRankMask;
+            else raise_err(err, kErrRange);
+        }
+        s_p[x] = pv;
+        s_r2[x] = r2;
+        s_lab[x] = lab;
+    }
+    __syncthreads();
+    const uint64_t rmask = (uint64_t(1) << rbits) - 1;
+    for (int li = kRunMax + threadIdx.x; li < kRunMax + kKrTile; li += kKrBlock) {
+        if (lo + li >= int64_t(A)) break;
+        // run start: the nearest first-of-run bit at or before li (at most kRunMax - 1 back)
+        int st = li;
+        while (!(s_p[st] & kDone) && li - st < kRunMax - 1) --st;
+        // run end: the next first-of-run bit after li (slots past A carry the bit)
+        int en = li + 1;
+        while (!(s_p[en] & kDone) && en - st < kRunMax) ++en;
+        if (!(s_p[st] & kDone) || !(s_p[en] & kDone)) {
+            raise_err(err, kErrRange);  // a run longer than kRunMax: not this kernel's case
+            continue;
+        }
+        const uint32_t r2 = s_r2[li];
+        uint32_t before = 0;
+        for (int y = st; y < en; ++y) {
+            const uint32_t q = s_r2[y];
+            before += (q < r2 || (q == r2 && y < li)) ? 1u : 0u;
+        }
+        const int64_t out = lo + st + before;
+        if (out >= int64_t(A)) {
+            raise_err(err, kErrRange);
+            continue;
+        }
+        K[out] = ((uint64_t(s_lab[st]) & rmask) << rbits) | (uint64_t(r2) & rmask);
+        V[out] = s_p[li] & kRankMask;
+    }
+}
+
+static int launch_keys_runs(const uint32_t *P, const uint32_t *S, const uint32_t *rank,
+                            int64_t a_bound, int64_t n, int rbits, const uint32_t *state,
+                            int count_word, uint64_t *K, uint32_t *V, uint32_t *err,
+                            hipStream_t s) {
+    int64_t tiles = (a_bound + kKrTile - 1) / kKrTile;
+    if (tiles < 1) tiles = 1;
+    // algorithmic bytes per item: read P, S and rank[p + h] (4 each); write K (8) and V (4)
+    TimedScope ts("keyruns", 0.0, 24.0, s);
+    hipLaunchKernelGGL(k_keys_runs, dim3(unsigned(tiles)), dim3(kKrBlock), 0, s, P, S, rank,
+                       uint32_t(n), rbits, state, count_word, K, V, err);
+    ts.finish();
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
 static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32_t *S,
                               int64_t a_bound, int64_t n, bool round0, int h0, int rbits,
-                              int32_t *sa, uint32_t *rank, uint32_t *S_new, uint64_t *lbflags,
-                              uint32_t *tick, uint32_t *state, hipStream_t s) {
+                              int32_t *sa, uint32_t *rank, uint32_t *S_new, uint32_t *P_new,
+                              uint64_t *lbflags, uint32_t *tick, uint32_t *state, hipStream_t s) {
     int64_t tiles = (a_bound + kRuTile - 1) / kRuTile;
     if (tiles < 1) tiles = 1;
     SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     // algorithmic bytes: read K (8) + V (4) + S (4 when present); write sa (4) + rank (4) +
-    // S_new (4, upper bound)
-    TimedScope ts = S ? TimedScope("rank_update", 0.0, 28.0, s)
-                      : TimedScope("rank_update", double(a_bound) * 24.0, s);
+    // S_new (4) + P_new (4) (upper bounds)
+    TimedScope ts = S ? TimedScope("rank_update", 0.0, 32.0, s)
+                      : TimedScope("rank_update", double(a_bound) * 28.0, s);
     hipLaunchKernelGGL(k_rank_update, dim3(unsigned(tiles)), dim3(kRuBlock), 0, s, K, V, S,
-                       uint32_t(n), int(round0), uint32_t(h0), rbits, sa, rank, S_new, lbflags,
-                       tick, state, state + kStErr);
+                       uint32_t(n), int(round0), uint32_t(h0), rbits, sa, rank, S_new, P_new,
+                       lbflags, tick, state, state + kStErr);
     ts.finish();
     SA_HIP(hipGetLastError());
     return SA_OK;
@@ -326,23 +431,35 @@ struct Build {
         int cur = 0;
         SA_TRY(sort_run(L.sb, 0, nullptr, n, 0, key0_bits, t, nparts, s, &cur));
         SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], nullptr, n, n, true, h0, rbits,
-                                  sa, rank, L.slots[0], L.lbflags, L.tickets, L.state, s));
+                                  sa, rank, L.slots[0], L.pos, L.lbflags, L.tickets, L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
     }
 
     // One doubling round reading its slots from slots[sl] and writing slots[sl ^ 1]; a_bound
-    // bounds the active count (grid and fill sizes).
-    int doubling_round(int sl, int64_t a_bound) {
-        const int bits = 2 * rbits;
-        SA_TRY(sort_prepare(L.sb, a_bound, bits, t, s));
-        int nparts = 0;
-        SA_TRY(launch_keys_doubling(rank, n, rbits, L.sb, 0, L.lbflags, L.tickets, L.state, t, s, &nparts));
+    // bounds the active count (grid and fill sizes).  Unless runs_only, both sorts are
+    // enqueued and exactly one does work, chosen on the device (state[kStBig]); both leave the
+    // sorted keys in the buffer the passes end in.  runs_only enqueues the run sort alone,
+    // for rounds after one whose groups all had at most kRunMax members: groups only split,
+    // so that stays true (a longer run would raise kErrRange).
+    int doubling_round(int sl, int64_t a_bound, bool runs_only = false) {
         int cur = 0;
-        SA_TRY(sort_run(L.sb, 0, L.state + kStActive, a_bound, 0, bits, t, nparts, s, &cur));
+        if (!runs_only) {
+            const int bits = 2 * rbits;
+            SA_TRY(sort_prepare(L.sb, a_bound, bits, t, s));
+            int nparts = 0;
+            timing_scope_mode(kModeRadix);
+            SA_TRY(launch_keys_doubling(rank, n, rbits, kStRadixN, L.sb, 0, L.lbflags, L.tickets, L.state, t, s, &nparts));
+            SA_TRY(sort_run(L.sb, 0, L.state + kStRadixN, a_bound, 0, bits, t, nparts, s, &cur));
+        }
+        timing_scope_mode(kModeRuns);
+        SA_TRY(launch_keys_runs(L.pos, L.slots[sl], rank, a_bound, n, rbits, L.state,
+                                runs_only ? kStActive : kStRunsN, L.sb.keys[cur], L.sb.vals[cur],
+                                L.state + kStErr, s));
+        timing_scope_mode(kModeAny);
         SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], L.slots[sl], a_bound, n, false, h0,
-                                  rbits, sa, rank, L.slots[sl ^ 1], L.lbflags, L.tickets, L.state, s));
+                                  rbits, sa, rank, L.slots[sl ^ 1], L.pos, L.lbflags, L.tickets, L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
@@ -413,18 +530,23 @@ struct Build {
             int cur = 0, sl = 0;
             int64_t bound = n;
             SA_TRY(snapshot(ps, cur));  // state after round 0
+            // Round 1 waits for round 0's state: if its groups are all small, no round needs
+            // the radix passes again.
+            SA_HIP(hipEventSynchronize(ps.ev[cur]));
+            bool runs_only = ps.h[8 * cur + kStBig] == 0;
             for (int guard = 0;; ++guard) {
                 if (guard > 40) return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
                 const int64_t tag = timing_round_begin();
-                SA_TRY(doubling_round(sl, bound));
+                SA_TRY(doubling_round(sl, bound, runs_only));
                 SA_TRY(snapshot(ps, cur ^ 1));
                 sl ^= 1;
                 SA_HIP(hipEventSynchronize(ps.ev[cur]));
                 memcpy(host, ps.h + 8 * cur, sizeof(uint32_t) * 8);
                 // the state before the round just enqueued holds that round's active count
-                timing_round_items(tag, host[kStActive]);
+                timing_round_items(tag, host[kStActive], host[kStBig] ? kModeRadix : kModeRuns);
                 timing_poll();
                 SA_TRY(check_err(host[kStErr]));
+                if (host[kStBig] == 0) runs_only = true;
                 cur ^= 1;
                 if (host[kStActive] == 0) {
                     // the round just enqueued is a no-op; wait for it so the stream is clean
