@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--p99-bound-ms", type=float, default=500.0, help="serving: p99 bound")
     ap.add_argument("--patterns", type=int, default=1_000_000, help="lookup: patterns per step")
     ap.add_argument("--pattern-len", type=int, default=40, help="lookup: pattern length")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "radix_pass_traffic.json"),
-                    help="JSON with HBM bytes per radix-pass launch from rocprofv3 counters")
+    ap.add_argument("--traffic-dir", default=os.path.join(ROOT, "profiles"),
+                    help="folder of <kernel>_traffic.json files: HBM bytes per launch from rocprofv3 counters")
     return ap.parse_args()
 
 
@@ -516,14 +516,18 @@ def main():
     L, ms, by = pkg.sa_timing_get(dom)
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     traffic = None
-    if dom == "radix_pass" and os.path.exists(args.traffic):
-        # counter-derived HBM bytes per launch, valid only for the kernel source they were taken on
+    # counter-derived HBM bytes per launch (<kernel key>_traffic.json), valid only for the
+    # source files the counters were taken on
+    sources = {"radix_pass": ("radix.hip", "device.hpp"),
+               "rank_update": ("sa_build.hip", "device.hpp", "internal.hpp")}
+    tpath = os.path.join(args.traffic_dir, f"{dom}_traffic.json")
+    if dom in sources and os.path.exists(tpath):
         import hashlib
         csrc = os.path.join(ROOT, "paper_1404_3456_amd", "csrc")
-        h = hashlib.sha256(open(os.path.join(csrc, "radix.hip"), "rb").read() +
-                           open(os.path.join(csrc, "device.hpp"), "rb").read()).hexdigest()
+        h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                    for f in sources[dom])).hexdigest()
         try:
-            tr = json.load(open(args.traffic))
+            tr = json.load(open(tpath))
             if tr.get("source_sha256") == h and tuning is None and args.sa_algo == "doubling":
                 traffic = tr.get("bytes_per_launch")
         except Exception:

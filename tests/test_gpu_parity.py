@@ -459,3 +459,44 @@ def test_overlaps_rc_sampled_large(lib):
     got = lib.sa_overlaps_rc(dev(r.text), r.min_len).cpu().numpy()
     want = oracle.overlaps_rc(r.text, r.min_len)
     assert got.shape[0] > 1000 and np.array_equal(got, want)
+
+
+def stem_family_text(seed):
+    """40 reads of 360 bases: a 60-base stem shared by all, then 8 families of 5 reads sharing
+    100 more bases, then a random 200-base tail each.  After the first round (29 bases) and the
+    next (58) the stem still holds groups of 40; from 116 bases on no group has more than 5."""
+    rng = np.random.default_rng([synth.SEED_BASE, 700, seed])
+    bases = np.frombuffer(b"ACGT", dtype=np.uint8)
+    stem = rng.choice(bases, 60)
+    reads = []
+    for _ in range(8):
+        fam = rng.choice(bases, 100)
+        for _ in range(5):
+            reads.append(np.concatenate([stem, fam, rng.choice(bases, 200)]).tobytes().decode())
+    return synth.text_from_strings(reads)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_build_switches_from_radix_rounds_to_run_sort(lib, seed):
+    """Rounds whose groups exceed 32 members sort by radix passes; once every group is small
+    the rounds sort group by group.  A build that goes through both must still give the
+    oracle's arrays, and the timing records show that both sorts did work."""
+    text = stem_family_text(seed)
+    n = text.size
+    tuning = {"digit_bits": 9, "block_threads": 512, "items_per_thread": 16}
+    lib.sa_timing_reset()
+    lib.sa_timing_enable(True)
+    try:
+        sa, isa, lcp, ovl = run_all(lib, text, 40, tuning=tuning)
+    finally:
+        lib.sa_timing_enable(False)
+    want = oracle.suffix_array(text)
+    assert np.array_equal(sa, want)
+    assert np.array_equal(isa[want], np.arange(n))
+    assert np.array_equal(lcp, oracle.lcp_array(text, want))
+    assert np.array_equal(ovl, oracle.overlaps(text, 40))
+    _, _, radix_bytes = lib.sa_timing_get("radix_pass")
+    _, _, runs_bytes = lib.sa_timing_get("keyruns")
+    first_round = 7 * n * 24.0  # 63-bit first-round keys, 9-bit digits, 24 B per item
+    assert radix_bytes > first_round, "no doubling round sorted by radix passes"
+    assert runs_bytes > 0, "no doubling round sorted group by group"
