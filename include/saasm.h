@@ -122,6 +122,13 @@ int sa_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int
 /* Workspace bytes for sa_build on a text of n bytes. */
 int64_t sa_build_ws_bytes(int64_t n, const sa_tuning *tune_or_null);
 
+/* One workspace for the whole path on a text of n bytes with at most n_reads_upper reads
+ * (<= 0: assume n): the largest of what sa_build (default tuning), sa_lcp and sa_overlaps need,
+ * the last with room for up to n candidate matches of its walks (a text with more makes
+ * sa_overlaps return SA_ERR_NOMEM with the size it needs).  The calls may share it because each
+ * finishes with it before the next starts on the same stream.  -1 for n < 1. */
+int64_t sa_workspace_bytes(int64_t n, int64_t n_reads_upper);
+
 /* sa_build: suffix array of the text.
  *   text         [n] bytes (see conventions)
  *   sa           [n] out: the permutation of 0..n-1 listing suffixes in sorted order
@@ -154,18 +161,21 @@ int sa_build_dc3(const uint8_t *text, int64_t n, int32_t *sa, int32_t *isa_or_nu
  *   sa          [n] out: for every s, sa[set_off_h[s] .. set_off_h[s+1]) is the suffix array
  *               of text s, in concatenated coordinates (subtract set_off_h[s] for local ones)
  *   isa_or_null [n] optional out: inverse of sa
+ *   lcp_or_null [n] optional out: the LCP array of each text in its block (lcp[set_off_h[s]]
+ *               is 0); the same array sa_lcp gives for the concatenated text.  A failure found
+ *               while computing it is reported the way sa_lcp reports it (in lcp[0]).
  *   use_graph   nonzero: the doubling rounds are recorded once as a hipGraph and replayed
  * The workspace size depends on the packing when tune->seg_pack > 0: pass the same offsets to
- * sa_build_batched_ws_bytes (NULL offsets give the size for one build of all texts).
- * sa_lcp and sa_overlaps accept the concatenated text with this sa/isa unchanged: LCP is 0 at
- * every block start and no overlap pairs reads of different texts.  Synchronises the stream
- * once per round (once per graph replay). */
+ * sa_build_batched_ws_bytes (NULL offsets give the size for one build of all texts); it
+ * includes the room the LCP needs.  sa_lcp and sa_overlaps accept the concatenated text with
+ * this sa/isa unchanged: LCP is 0 at every block start and no overlap pairs reads of different
+ * texts.  Synchronises the stream once per round (once per graph replay). */
 int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const int64_t *set_off_h_or_null,
                                   const sa_tuning *tune_or_null);
 int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h, int32_t n_sets,
-                     int32_t *sa, int32_t *isa_or_null, void *ws, int64_t ws_bytes,
-                     const sa_tuning *tune_or_null, int32_t use_graph, int32_t *rounds_h,
-                     hipStream_t stream);
+                     int32_t *sa, int32_t *isa_or_null, int32_t *lcp_or_null, void *ws,
+                     int64_t ws_bytes, const sa_tuning *tune_or_null, int32_t use_graph,
+                     int32_t *rounds_h, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* LCP array beside the suffix array (Kasai's permuted-LCP scan; the paper uses the array for  */
@@ -176,9 +186,16 @@ int64_t sa_lcp_ws_bytes(int64_t n);
 
 /* sa_lcp: lcp[0] = 0 and lcp[i] = length of the common prefix of the suffixes at sa[i-1] and
  * sa[i]; separators never match.  sa and isa must come from sa_build on the same text
- * (isa[sa[i]] == i).  Does not synchronise. */
+ * (isa[sa[i]] == i).  Does not synchronise, so failures that only the device can see (a byte
+ * other than A, C, G, T, '$'; a text without its final '$'; sa/isa entries out of range) are
+ * reported in the output: lcp[0] then holds the negative status (SA_ERR_ALPHABET,
+ * SA_ERR_INVALID or SA_ERR_HIP) instead of 0.  sa_lcp_status reads it; sa_overlaps returns it. */
 int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
            int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream);
+
+/* sa_lcp_status: synchronises `stream` and returns the status an earlier sa_lcp (or
+ * sa_build_batched with an LCP output) on that stream left in lcp[0]: SA_OK when it is 0. */
+int sa_lcp_status(const int32_t *lcp, hipStream_t stream);
 
 /* Positions scanned per thread by sa_lcp: 1, 2, 4, 8 or 16 (each thread restarts Kasai's
  * carried bound at its first position; any value gives the same result).  Process-wide;
@@ -319,7 +336,17 @@ typedef struct {
  *                       different workers run concurrently on the device
  *   mode                0: continuous batching; 1: plain (one job at a time, one worker, the
  *                       single-text entry points) -- the per-job baseline
- * The server uses the device current at creation. */
+ * The server uses the device current at creation.  It takes a worker count instead of one
+ * caller stream: a batch admitted while another is on the device must run on a stream of its
+ * own to overlap with it, so each worker owns one (non-blocking, default priority).  Callers
+ * order their own work after a job through asm_poll, which reports a job done only once its
+ * results are complete in device memory.
+ * Admission: queued jobs are laid into a batch while their memory fits.  When a batch of
+ * several jobs does not fit, half as many are tried at once (the full batch size returns with
+ * the next admission that fits).  A single job that does not fit waits until a batch ends or
+ * the caller releases a finished job (asm_release); it fails with SA_ERR_NOMEM only when it
+ * does not fit in an empty arena.  Finished jobs hold their memory until released, so a
+ * caller that never releases can leave later jobs waiting. */
 int asm_server_create(void *arena, int64_t arena_bytes, int32_t max_jobs_per_batch,
                       int32_t workers, int32_t mode, asm_server **out);
 
@@ -360,12 +387,21 @@ int asm_server_destroy(asm_server *server);
 /* ---------------------------------------------------------------------------------------- */
 
 /* Per-kernel timing with HIP events recorded on the launch stream around every instrumented
- * launch.  Keys: "radix_pass", "keybuild", "rank_update", "kasai", "overlap_walk", "pack".
+ * launch.  Keys: "radix_pass", "key0" (first-round keys), "keybuild" (doubling keys in text
+ * order), "keyruns" (doubling keys sorted run by run), "rank_update", "kasai", "lcp_gather",
+ * "overlap_walk", "pack", "lookup".
  * sa_timing_get returns launches, summed duration (ms) and summed algorithmic bytes (the
  * bytes each launch must move at minimum, as documented per kernel). */
 int sa_timing_enable(int32_t on);
 int sa_timing_reset(void);
 int sa_timing_get(const char *key, int64_t *launches_h, double *total_ms_h, double *bytes_h);
+
+/* sa_timing_items: summed units of work of the timed launches under `key` (suffixes for
+ * "pack", "key0", "kasai" and "lcp_gather"; items sorted for "radix_pass"; active suffixes
+ * for "rank_update", "keyruns" and "keybuild"; reads for
+ * "overlap_walk"; patterns for "lookup"), so that bytes per unit of any other model can be
+ * applied to the same launches. */
+int sa_timing_items(const char *key, double *items_h);
 
 /* sa_copy_u32: plain device copy of n words (dst[i] = src[i]); a reference kernel of known
  * traffic for calibrating hardware byte counters.  Does not synchronise. */

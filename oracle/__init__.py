@@ -56,6 +56,8 @@ def _load():
         lib.oracle_num_reads.restype = I64
         lib.oracle_check_adjacent.argtypes = [P, I64, P, P, P, I64, P, ctypes.c_int]
         lib.oracle_check_adjacent.restype = I64
+        lib.oracle_check_range.argtypes = [P, I64, P, P, I64, I64, P, ctypes.c_int]
+        lib.oracle_check_range.restype = I64
         lib.oracle_lookup.argtypes = [P, I64, P, P, I64, P, ctypes.c_int]
         lib.oracle_lookup.restype = ctypes.c_int
         _lib = lib
@@ -150,6 +152,26 @@ def check_adjacent(text, sa, lcp, idx, nthreads=None):
     first = ctypes.c_int64(-1)
     bad = _load().oracle_check_adjacent(_ptr(t), t.size, _ptr(sa), lp, _ptr(idx), idx.size,
                                         ctypes.byref(first), _threads(nthreads))
+    return int(bad), int(first.value)
+
+
+def check_all(text, sa, lcp, lo=1, hi=None, nthreads=None):
+    """Exhaustive check of the adjacent pairs with index in [lo, hi) (default: all of them):
+    suffix sa[i-1] < suffix sa[i], and lcp[i] (if lcp is given) equals the direct common prefix.
+    With sa a permutation (checked by the caller) this pins sa and lcp element by element.
+    Returns (n_bad, first_bad_index)."""
+    t = _text(text)
+    sa = np.ascontiguousarray(sa, dtype=np.int32)
+    if sa.size != t.size:
+        raise ValueError("sa and text differ in length")
+    lp = None
+    if lcp is not None:
+        lcp = np.ascontiguousarray(lcp, dtype=np.int32)
+        lp = _ptr(lcp)
+    hi = t.size if hi is None else int(hi)
+    first = ctypes.c_int64(-1)
+    bad = _load().oracle_check_range(_ptr(t), t.size, _ptr(sa), lp, int(lo), hi,
+                                     ctypes.byref(first), _threads(nthreads))
     return int(bad), int(first.value)
 
 

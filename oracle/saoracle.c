@@ -367,6 +367,68 @@ int64_t oracle_check_adjacent(const uint8_t *t, int64_t n, const int32_t *sa, co
     return bad;
 }
 
+/* Every index i in [lo, hi) (1 <= lo): 1 if sa[i-1] < sa[i] in suffix order and lcp[i] (if
+ * lcp != NULL) equals the direct common prefix.  Together with a check that sa is a
+ * permutation this is the whole suffix-array definition: a permutation whose adjacent suffixes
+ * all ascend is the sorted order.  Returns the number of failures; the first failing index
+ * goes to *first_bad (or -1).
+ *
+ * The same comparison as suffix_cmp / oracle_lcp_pair, organised for full-size texts: whole
+ * 8-byte words are skipped while they agree and hold no separator (a word holds the byte '$'
+ * exactly when some byte of w ^ 0x24..24 is zero, and a word v has a zero byte exactly when
+ * (v - 0x01..01) & ~v & 0x80..80 is non-zero); the bytes from there on are compared one by one
+ * as oracle_lcp_pair does, and the bytes where that stops decide the order as suffix_cmp does.
+ * The test suite pins it against the byte-by-byte check above. */
+static int has_sep_byte(uint64_t w)
+{
+    const uint64_t v = w ^ 0x2424242424242424ull;
+    return ((v - 0x0101010101010101ull) & ~v & 0x8080808080808080ull) != 0;
+}
+
+int64_t oracle_check_range(const uint8_t *t, int64_t n, const int32_t *sa, const int32_t *lcp,
+                           int64_t lo, int64_t hi, int64_t *first_bad, int nthreads)
+{
+    if (text_ok(t, n)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (lo < 1) lo = 1;
+    if (hi > n) hi = n;
+    int64_t bad = 0, first = -1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 65536) reduction(+:bad)
+    for (int64_t i = lo; i < hi; ++i) {
+        int ok = 1;
+        const int64_t p = sa[i - 1], q = sa[i];
+        if (p < 0 || p >= n || q < 0 || q >= n || p == q) ok = 0;
+        else {
+            int64_t k = 0;
+            /* both suffixes end with a separator, so neither word read passes t[n-1] while no
+             * separator has been met: p + k + 8 <= n holds whenever the word holds none */
+            while (p + k + 8 <= n && q + k + 8 <= n) {
+                uint64_t a, b;
+                memcpy(&a, t + p + k, 8);
+                memcpy(&b, t + q + k, 8);
+                if (a != b || has_sep_byte(a)) break;
+                k += 8;
+            }
+            while (t[p + k] == t[q + k] && t[p + k] != SEPB) ++k;
+            const uint8_t x = t[p + k], y = t[q + k];
+            int less;
+            if (x == SEPB && y == SEPB) less = p < q;
+            else if (x == SEPB) less = 1;
+            else if (y == SEPB) less = 0;
+            else less = x < y;
+            if (!less) ok = 0;
+            if (lcp && lcp[i] != k) ok = 0;
+        }
+        if (!ok) {
+            ++bad;
+#pragma omp critical
+            { if (first < 0 || i < first) first = i; }
+        }
+    }
+    if (first_bad) *first_bad = first;
+    return bad;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* Pattern lookup: the SA interval of the suffixes that start with a pattern (see header).   */
 /* ---------------------------------------------------------------------------------------- */

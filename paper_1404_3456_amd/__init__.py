@@ -30,6 +30,7 @@ from ._abi import (  # noqa: F401
     sa_build_ws_bytes,
     sa_copy_u32,
     sa_lcp,
+    sa_lcp_status,
     sa_lcp_plcp_min,
     sa_lcp_set_chunk,
     sa_lcp_ws_bytes,
@@ -43,11 +44,14 @@ from ._abi import (  # noqa: F401
     sa_overlaps,
     sa_overlaps_ws_bytes,
     sa_pack,
+    sa_path,
     sa_sort_pairs,
     sa_sort_ws_bytes,
     sa_timing_enable,
     sa_timing_get,
+    sa_timing_items,
     sa_timing_reset,
     sa_version,
     sa_last_error,
+    sa_workspace_bytes,
 )

@@ -79,7 +79,9 @@ def load():
         "sa_build_dc3_ws_bytes": ([I64, TP], I64),
         "sa_build_dc3": ([P, I64, P, P, P, I64, TP, P, P], ctypes.c_int),
         "sa_build_batched_ws_bytes": ([I64, I32, P, TP], I64),
-        "sa_build_batched": ([P, I64, P, I32, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
+        "sa_build_batched": ([P, I64, P, I32, P, P, P, P, I64, TP, I32, P, P], ctypes.c_int),
+        "sa_workspace_bytes": ([I64, I64], I64),
+        "sa_lcp_status": ([P, P], ctypes.c_int),
         "sa_lcp_ws_bytes": ([I64], I64),
         "sa_lookup_ws_bytes": ([I64, I64], I64),
         "sa_reconstruct": ([P, I64, P, P, P, P, P, I64, P, I64], ctypes.c_int),
@@ -95,6 +97,7 @@ def load():
         "sa_timing_enable": ([I32], ctypes.c_int),
         "sa_timing_reset": ([], ctypes.c_int),
         "sa_timing_get": ([ctypes.c_char_p, P, P, P], ctypes.c_int),
+        "sa_timing_items": ([ctypes.c_char_p, P], ctypes.c_int),
         "sa_copy_u32": ([P, P, I64, P], ctypes.c_int),
         "asm_server_create": ([P, I64, I32, I32, I32, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
         "asm_submit": ([P, P, I64, I32, I32, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -271,10 +274,11 @@ def sa_build_batched_ws_bytes(n: int, n_sets: int, tuning=None, set_off=None) ->
 
 
 def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bool = True,
-                     stream=None, return_rounds: bool = False):
+                     stream=None, return_rounds: bool = False, lcp: bool = False):
     """Suffix arrays of many texts laid end to end.  `set_off` (host, int64, n_sets+1) bounds
     text s as text[set_off[s]:set_off[s+1]].  Returns (sa, isa) in concatenated coordinates:
-    sa[set_off[s]:set_off[s+1]] is the suffix array of text s."""
+    sa[set_off[s]:set_off[s+1]] is the suffix array of text s; with lcp=True, (sa, isa, lcp)
+    where lcp is computed inside the same call (its status is checked)."""
     import numpy as np
     torch = _torch()
     lib = load()
@@ -289,15 +293,21 @@ def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bo
         raise SaasmError(SA_ERR_INVALID, "bad size, set count or tuning")
     ws = _ws(wsb, t.device)
     rounds = ctypes.c_int32(0)
+    lcp_t = torch.empty(n, dtype=torch.int32, device=t.device) if lcp else None
     _check(lib.sa_build_batched(_ptr(t), n, off.ctypes.data_as(ctypes.c_void_p), n_sets, _ptr(sa),
-                                _ptr(isa_t), _ptr(ws), ws.numel(), _tune(tuning),
+                                _ptr(isa_t), _ptr(lcp_t), _ptr(ws), ws.numel(), _tune(tuning),
                                 1 if use_graph else 0, ctypes.byref(rounds), _stream(stream)))
+    if lcp:
+        _check(lib.sa_lcp_status(_ptr(lcp_t), _stream(stream)))
+    res = (sa, isa_t, lcp_t) if lcp else (sa, isa_t)
     if return_rounds:
-        return sa, isa_t, int(rounds.value)
-    return sa, isa_t
+        return (*res, int(rounds.value))
+    return res
 
 
-def sa_lcp(text, sa, isa, stream=None):
+def sa_lcp(text, sa, isa, stream=None, check: bool = False):
+    """LCP array (asynchronous).  A failure only the device sees is left in lcp[0] as a
+    negative status; check=True waits for it (sa_lcp_status) and raises."""
     torch = _torch()
     lib = load()
     t = _dev_text(text)
@@ -306,7 +316,49 @@ def sa_lcp(text, sa, isa, stream=None):
     ws = _ws(sa_lcp_ws_bytes(n), t.device)
     _check(lib.sa_lcp(_ptr(t), n, _ptr(sa), _ptr(isa), _ptr(lcp), _ptr(ws), ws.numel(),
                       _stream(stream)))
+    if check:
+        sa_lcp_status(lcp, stream)
     return lcp
+
+
+def sa_lcp_status(lcp, stream=None):
+    """Waits for the stream and raises SaasmError when sa_lcp left a failure in lcp[0]."""
+    _check(load().sa_lcp_status(_ptr(lcp), _stream(stream)))
+
+
+def sa_workspace_bytes(n: int, n_reads_upper: int = 0) -> int:
+    return int(load().sa_workspace_bytes(int(n), int(n_reads_upper)))
+
+
+def sa_path(text, min_len: int, stream=None, ws=None):
+    """The whole path -- sa_build, sa_lcp, sa_overlaps -- through one workspace of
+    sa_workspace_bytes(n, reads) bytes (allocated here unless `ws` is given): (sa, isa, lcp,
+    overlap rows)."""
+    torch = _torch()
+    lib = load()
+    t = _dev_text(text)
+    n = t.numel()
+    if ws is None:
+        ws = _ws(sa_workspace_bytes(n, 0), t.device)
+    sa = torch.empty(n, dtype=torch.int32, device=t.device)
+    isa_t = torch.empty(n, dtype=torch.int32, device=t.device)
+    lcp = torch.empty(n, dtype=torch.int32, device=t.device)
+    st = _stream(stream)
+    _check(lib.sa_build(_ptr(t), n, _ptr(sa), _ptr(isa_t), _ptr(ws), ws.numel(), None, None, st))
+    _check(lib.sa_lcp(_ptr(t), n, _ptr(sa), _ptr(isa_t), _ptr(lcp), _ptr(ws), ws.numel(), st))
+    cap = max(n // 64, 1024)
+    for _ in range(4):
+        out = torch.empty((cap, 3), dtype=torch.int32, device=t.device)
+        n_out = ctypes.c_int64(0)
+        needed = ctypes.c_int64(0)
+        rc = lib.sa_overlaps(_ptr(t), n, _ptr(sa), _ptr(isa_t), _ptr(lcp), int(min_len), _ptr(out),
+                             cap, ctypes.byref(n_out), _ptr(ws), ws.numel(), ctypes.byref(needed), st)
+        if rc == SA_ERR_CAPACITY and n_out.value > cap:
+            cap = int(n_out.value)
+            continue
+        _check(rc)
+        return sa, isa_t, lcp, out[: n_out.value]
+    raise SaasmError(SA_ERR_HIP, "sa_path: sizes did not settle")
 
 
 def sa_lookup_ws_bytes(n: int, pat_total: int) -> int:
@@ -479,6 +531,15 @@ def sa_timing_get(key: str):
     if rc not in (SA_OK, SA_ERR_NOTFOUND):
         _check(rc)
     return int(L.value), float(ms.value), float(by.value)
+
+
+def sa_timing_items(key: str) -> float:
+    """Summed units of work (suffixes, items, reads) of the timed launches under `key`."""
+    v = ctypes.c_double(0.0)
+    rc = load().sa_timing_items(key.encode(), ctypes.byref(v))
+    if rc not in (SA_OK, SA_ERR_NOTFOUND):
+        _check(rc)
+    return float(v.value)
 
 
 def sa_copy_u32(dst, src, stream=None):

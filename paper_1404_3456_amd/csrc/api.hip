@@ -44,6 +44,7 @@ struct Acc {
     int64_t launches = 0;
     double ms = 0.0;
     double bytes = 0.0;
+    double items = 0.0;
 };
 struct Pending {
     hipEvent_t a, b;
@@ -52,6 +53,7 @@ struct Pending {
     double per_item;
     int64_t tag;  // -1: bytes final; else waiting for timing_round_items
     int mode;     // kModeAny, or the round sort mode these bytes belong to
+    double items; // units of work the launch processed
 };
 std::atomic<int64_t> g_next_tag{1};
 thread_local int64_t t_tag = -1;
@@ -82,7 +84,8 @@ bool timing_on() { return g_on && !t_pause; }
 
 void timing_pause(bool on) { t_pause = on; }
 
-TimedScope::TimedScope(const char *k, double b, hipStream_t s) : key(k), bytes(b), stream(s) {
+TimedScope::TimedScope(const char *k, double b, hipStream_t s, double n_items)
+    : key(k), bytes(b), items(n_items), stream(s) {
     if (!g_on || t_pause) return;
     std::lock_guard<std::mutex> lk(g_mu);
     start = get_event();
@@ -109,7 +112,7 @@ void TimedScope::finish() {
         start = nullptr;
         return;
     }
-    g_pending.push_back(Pending{start, end, key, bytes, per_item, tag, mode});
+    g_pending.push_back(Pending{start, end, key, bytes, per_item, tag, mode, items});
     start = nullptr;
 }
 
@@ -126,6 +129,7 @@ void timing_round_items(int64_t tag, int64_t items, int mode) {
         // are the kernels of the sort mode the round did not use
         const bool used = p.mode == kModeAny || p.mode == mode;
         p.bytes = items <= 0 || !used ? 0.0 : p.bytes + p.per_item * double(items);
+        p.items = items <= 0 || !used ? 0.0 : double(items);
         p.tag = -1;
     }
 }
@@ -147,7 +151,7 @@ static void timing_resolve(bool block) {
         }
         // a launch whose round count never arrived belongs to a round the build did not need
         // (it found nothing active): timed, no bytes
-        if (p.tag >= 0) p.bytes = 0.0;
+        if (p.tag >= 0) p.bytes = p.items = 0.0;
         float ms = 0.f;
         if (hipEventSynchronize(p.b) == hipSuccess &&
             hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -155,6 +159,7 @@ static void timing_resolve(bool block) {
             a.launches += 1;
             a.ms += ms;
             a.bytes += p.bytes;
+            a.items += p.items;
         }
         g_pool.push_back(p.a);
         g_pool.push_back(p.b);
@@ -205,8 +210,21 @@ static int sa_timing_get_impl(const char *key, int64_t *launches_h, double *tota
     return SA_OK;
 }
 
+static int sa_timing_items_impl(const char *key, double *items_h) {
+    if (!key || !items_h) return fail(SA_ERR_INVALID, "sa_timing_items: NULL pointer");
+    timing_flush();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_acc.find(key);
+    *items_h = it == g_acc.end() ? 0.0 : it->second.items;
+    return it == g_acc.end() ? SA_ERR_NOTFOUND : SA_OK;
+}
+
 // ---- C entry points: bodies above, host exceptions turned into statuses ------------------
 extern "C" int sa_timing_get(const char *key, int64_t *launches_h, double *total_ms_h,
                              double *bytes_h) {
     return guard<int>([&] { return sa_timing_get_impl(key, launches_h, total_ms_h, bytes_h); });
+}
+
+extern "C" int sa_timing_items(const char *key, double *items_h) {
+    return guard<int>([&] { return sa_timing_items_impl(key, items_h); });
 }

@@ -81,14 +81,17 @@ struct TimedScope {
     // files the launch under `key` with `bytes` algorithmic bytes.  The second form is for
     // launches whose item count is only known on the device: the record waits until
     // timing_round_items() gives the count for the calling thread's current round tag.
+    // `items` counts the launch's units of work (suffixes, reads, pass items); the per-item
+    // form takes it from its round's count.
     const char *key;
     double bytes;
     double per_item = 0.0;
+    double items = 0.0;
     int64_t tag = -1;
     int mode = 0;
     hipStream_t stream;
     hipEvent_t start = nullptr;
-    TimedScope(const char *k, double b, hipStream_t s);
+    TimedScope(const char *k, double b, hipStream_t s, double n_items = 0.0);
     TimedScope(const char *k, double fixed_bytes, double per_item_bytes, hipStream_t s);
     void finish();
 };
@@ -123,6 +126,12 @@ int launch_read_ends(const uint32_t *sepmask, const int32_t *sepcnt, int64_t n, 
                      hipStream_t s);
 int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 int launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+
+// LCP array (Kasai's scan; lcp.hip): workspace bytes and the body of sa_lcp.  A failure found
+// on the device is written to flag[0] (default: lcp[0]) as the negative status.
+int64_t lcp_ws_bytes(int64_t n);
+int lcp_run(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa, int32_t *lcp,
+            void *ws, int64_t ws_bytes, hipStream_t stream, int32_t *flag = nullptr);
 
 // radix sort plumbing
 struct SortBufs {

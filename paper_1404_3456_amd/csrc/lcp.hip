@@ -109,7 +109,19 @@ static void launch_kasai(bool plcp, dim3 grid, hipStream_t s, const uint4 *blk, 
 
 using namespace saasm;
 
-extern "C" int64_t sa_lcp_ws_bytes(int64_t n) {
+namespace saasm {
+
+// A failure the device found while computing the array (a byte other than A, C, G, T, '$'; a
+// text without its final separator; an index out of range) replaces lcp[0], which is 0 in
+// every valid array, by the negative status -- so an asynchronous call can still report it.
+__global__ void k_lcp_flag(const uint32_t *err, int32_t *lcp) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t e = *err;
+    if (e == 0) return;
+    lcp[0] = (e & kErrAlphabet) ? SA_ERR_ALPHABET : (e & kErrNoSepEnd) ? SA_ERR_INVALID : SA_ERR_HIP;
+}
+
+int64_t lcp_ws_bytes(int64_t n) {
     if (n < 1) return -1;
     Carver c(nullptr, INT64_MAX);
     c.take<uint32_t>(packed_words(n));
@@ -121,12 +133,9 @@ extern "C" int64_t sa_lcp_ws_bytes(int64_t n) {
     return c.off + 256;
 }
 
-extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
-                      int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream) {
-    if (!text || !sa || !isa || !lcp || !ws) return fail(SA_ERR_INVALID, "sa_lcp: NULL pointer");
-    if (n < 1) return fail(SA_ERR_INVALID, "sa_lcp: n must be >= 1");
-    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_lcp: n >= 2^31-2");
-    if (ws_bytes < sa_lcp_ws_bytes(n)) return fail(SA_ERR_NOMEM, "sa_lcp: workspace too small");
+int lcp_run(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa, int32_t *lcp,
+            void *ws, int64_t ws_bytes, hipStream_t stream, int32_t *flag) {
+    if (ws_bytes < lcp_ws_bytes(n)) return fail(SA_ERR_NOMEM, "sa_lcp: workspace too small");
     Carver c(ws, ws_bytes);
     uint32_t *packed = c.take<uint32_t>(packed_words(n));
     uint32_t *sepmask = c.take<uint32_t>(sepmask_words(n));
@@ -144,7 +153,7 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
     int32_t *out = plcp ? pl : lcp;
     {
         // algorithmic bytes: isa[p] (4) + sa[isa[p]-1] (4) + lcp write (4) per position
-        TimedScope ts("kasai", double(n) * 12.0, stream);
+        TimedScope ts("kasai", double(n) * 12.0, stream, double(n));
         switch (chunk) {
             case 1: launch_kasai<1>(plcp, grid, stream, blk, sa, isa, out, uint32_t(n), err); break;
             case 2: launch_kasai<2>(plcp, grid, stream, blk, sa, isa, out, uint32_t(n), err); break;
@@ -157,7 +166,7 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
     }
     if (plcp) {
         // sa[i] (4) + plcp[sa[i]] (4) + lcp[i] (4)
-        TimedScope ts("kasai", double(n) * 12.0, stream);
+        TimedScope ts("lcp_gather", double(n) * 12.0, stream, double(n));
         int64_t g = (n + 255) / 256;
         if (g > 8192) g = 8192;
         hipLaunchKernelGGL(k_lcp_gather, dim3(unsigned(g)), dim3(256), 0, stream, sa, pl, lcp,
@@ -165,7 +174,33 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
         ts.finish();
         SA_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(k_lcp_flag, dim3(1), dim3(64), 0, stream, err, flag ? flag : lcp);
+    SA_HIP(hipGetLastError());
     return SA_OK;
+}
+
+}  // namespace saasm
+
+extern "C" int64_t sa_lcp_ws_bytes(int64_t n) { return lcp_ws_bytes(n); }
+
+extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
+                      int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream) {
+    if (!text || !sa || !isa || !lcp || !ws) return fail(SA_ERR_INVALID, "sa_lcp: NULL pointer");
+    if (n < 1) return fail(SA_ERR_INVALID, "sa_lcp: n must be >= 1");
+    if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_lcp: n >= 2^31-2");
+    return lcp_run(text, n, sa, isa, lcp, ws, ws_bytes, stream);
+}
+
+// Waits for the stream and reports the status sa_lcp left in lcp[0].
+extern "C" int sa_lcp_status(const int32_t *lcp, hipStream_t stream) {
+    if (!lcp) return fail(SA_ERR_INVALID, "sa_lcp_status: NULL pointer");
+    int32_t v = 0;
+    SA_HIP(hipMemcpyAsync(&v, lcp, 4, hipMemcpyDeviceToHost, stream));
+    SA_HIP(hipStreamSynchronize(stream));
+    if (v == 0) return SA_OK;
+    if (v == SA_ERR_ALPHABET) return fail(v, "sa_lcp: text holds a byte other than A, C, G, T, $");
+    if (v == SA_ERR_INVALID) return fail(v, "sa_lcp: text must end with '$'");
+    return fail(SA_ERR_HIP, "sa_lcp: device consistency check failed (sa/isa out of range)");
 }
 
 // Size from which sa_lcp takes the permuted-LCP form; returns the previous setting (min_n < 0:

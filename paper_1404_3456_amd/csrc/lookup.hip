@@ -170,7 +170,7 @@ extern "C" int sa_lookup(const uint8_t *text, int64_t n, const int32_t *sa, cons
     SA_HIP(hipGetLastError());
     {
         // algorithmic bytes: the pattern and its two result words
-        TimedScope ts("lookup", double(pat_total) + 8.0 * double(n_pat), stream);
+        TimedScope ts("lookup", double(pat_total) + 8.0 * double(n_pat), stream, double(n_pat));
         hipLaunchKernelGGL(k_lookup, dim3(unsigned((int64_t(n_pat) + 255) / 256)), dim3(256), 0,
                            stream, blk, sa, uint32_t(n), ppk, pat_off, pat_total,
                            uint32_t(n_pat), lohi, err);

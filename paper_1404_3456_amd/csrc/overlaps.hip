@@ -198,9 +198,15 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     SA_TRY(launch_scan_u32_i32(F.wordcnt, F.sepcnt, nw, reinterpret_cast<int32_t *>(F.ctr + 2),
                                F.lbflags, F.tick, F.ctr, s));
     uint32_t host[4];
+    int32_t lcp0 = 0;
     SA_HIP(hipMemcpyAsync(host, F.ctr, 16, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipMemcpyAsync(&lcp0, lcp, 4, hipMemcpyDeviceToHost, s));
     SA_HIP(hipStreamSynchronize(s));
     timing_flush();
+    // sa_lcp leaves a failure it found on the device in lcp[0] (0 in every valid array)
+    if (lcp0 < 0) return fail(lcp0 == SA_ERR_ALPHABET || lcp0 == SA_ERR_INVALID ? lcp0 : SA_ERR_HIP,
+                              "sa_overlaps: the LCP array carries a failure from sa_lcp");
+    if (lcp0 != 0) return fail(SA_ERR_INVALID, "sa_overlaps: lcp[0] must be 0");
     if (host[0] & kErrAlphabet) return fail(SA_ERR_ALPHABET, "text holds a byte other than A, C, G, T, $");
     if (host[0] & kErrNoSepEnd) return fail(SA_ERR_INVALID, "text must end with '$'");
     if (host[0]) return fail(SA_ERR_HIP, "device consistency check failed");
@@ -218,7 +224,7 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     // count candidates per read, then scan to offsets
     const unsigned rgrid = unsigned((m + 255) / 256);
     {
-        TimedScope ts("overlap_walk", double(m) * 12.0, s);
+        TimedScope ts("overlap_walk", double(m) * 12.0, s, double(m));
         hipLaunchKernelGGL(k_ovl_walk<false>, dim3(rgrid), dim3(256), 0, s, sa, isa, lcp,
                            F.read_end, F.sepmask, F.sepcnt, uint32_t(n), uint32_t(m), min_len,
                            F.counts, nullptr, nullptr, nullptr, F.ctr);
@@ -247,7 +253,7 @@ extern "C" int sa_overlaps(const uint8_t *text, int64_t n, const int32_t *sa, co
     H.sb.err = F.ctr;
     SA_TRY(launch_fill_u32(F.tick, 64, 0, s));
     {
-        TimedScope ts("overlap_walk", double(m) * 12.0 + double(r) * 12.0, s);
+        TimedScope ts("overlap_walk", double(m) * 12.0 + double(r) * 12.0, s, double(m));
         hipLaunchKernelGGL(k_ovl_walk<true>, dim3(rgrid), dim3(256), 0, s, sa, isa, lcp,
                            F.read_end, F.sepmask, F.sepcnt, uint32_t(n), uint32_t(m), min_len,
                            nullptr, F.offs, H.sb.keys[0], H.sb.vals[0], F.ctr);

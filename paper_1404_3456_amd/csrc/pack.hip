@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_pack(const uint8_t *__restrict__ text, 
 int launch_pack(const uint8_t *text, int64_t n, uint32_t *packed, uint32_t *sepmask,
                 uint32_t *wordcnt, uint32_t *err, hipStream_t s) {
     int64_t nw = sepmask_words(n);
-    TimedScope ts("pack", double(n) + double(nw) * 16.0, s);
+    TimedScope ts("pack", double(n) + double(nw) * 16.0, s, double(n));
     hipLaunchKernelGGL(k_pack, dim3(unsigned((nw + 255) / 256)), dim3(256), 0, s, text, n, packed,
                        sepmask, wordcnt, nw, err);
     ts.finish();

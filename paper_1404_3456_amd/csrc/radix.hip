@@ -460,7 +460,7 @@ int sort_run(const SortBufs &b, int cur, const uint32_t *count_dev, int64_t n, i
         const uint32_t shift = uint32_t(bit_lo + lo);
         const uint32_t dmask = (1u << width) - 1u;
         TimedScope ts = count_dev ? TimedScope("radix_pass", 0.0, 24.0, s)
-                                  : TimedScope("radix_pass", double(n) * 24.0, s);
+                                  : TimedScope("radix_pass", double(n) * 24.0, s, double(n));
         int rc = SA_OK;
         uint32_t *fl = b.flags + size_t(p) * tiles * R;
         switch (t.dbits) {
@@ -547,7 +547,7 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
     const int P = sort_passes(key_bits, t);
     *nparts = int(hist_grid(n));
     size_t lds = size_t(P) * t.radix() * 4;
-    TimedScope ts("keybuild", double(n) * (12.0 + 0.375), s);
+    TimedScope ts("key0", double(n) * (12.0 + 0.375), s, double(n));
     const unsigned g = hist_grid(n);
     switch (t.dbits) {
         case 4: hipLaunchKernelGGL(k_key0<4>, dim3(g), dim3(kK0Block), lds, s, packed, sepmask, uint32_t(n), uint32_t(h0), set_off_dev, uint32_t(n_sets), b.keys[cur], b.vals[cur], P, b.hist); break;

@@ -234,6 +234,8 @@ struct BuildLayout {
     uint32_t *tickets;
     uint32_t *state;       // kSt* words
     int64_t *set_off;      // batched builds: [n_sets + 1]
+    void *lcp_ws;          // batched builds: workspace of the LCP computed after the build
+    int64_t lcp_ws_bytes;
 };
 
 static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLayout *L) {
@@ -251,6 +253,8 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
     L->tickets = c.take<uint32_t>(64);
     L->state = c.take<uint32_t>(64);
     L->set_off = c.take<int64_t>(n_sets + 1);
+    L->lcp_ws_bytes = n_sets > 0 ? lcp_ws_bytes(n) : 0;
+    L->lcp_ws = n_sets > 0 ? c.take<char>(L->lcp_ws_bytes) : nullptr;
 }
 
 // Keys of a doubling round built in the previous round's sorted order, sorted group by group
@@ -351,7 +355,7 @@ static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32
     // algorithmic bytes: read K (8) + V (4) + S (4 when present); write sa (4) + rank (4) +
     // S_new (4) + P_new (4) (upper bounds)
     TimedScope ts = S ? TimedScope("rank_update", 0.0, 32.0, s)
-                      : TimedScope("rank_update", double(a_bound) * 28.0, s);
+                      : TimedScope("rank_update", double(a_bound) * 28.0, s, double(a_bound));
     hipLaunchKernelGGL(k_rank_update, dim3(unsigned(tiles)), dim3(kRuBlock), 0, s, K, V, S,
                        uint32_t(n), int(round0), uint32_t(h0), rbits, sa, rank, S_new, P_new,
                        lbflags, tick, state, state + kStErr);
@@ -564,10 +568,13 @@ struct Build {
     }
 };
 
+// lcp_or_null (batched builds only): the LCP array of this build's texts is computed after it
+// from the final labels; a failure found on the device goes to lcp_flag[0].
 static int build_common(const uint8_t *text, int64_t n, const int64_t *set_off_h, int32_t n_sets,
                         int32_t *sa, int32_t *isa_or_null, void *ws, int64_t ws_bytes,
                         const sa_tuning *tune, bool use_graph, int32_t *rounds_h,
-                        hipStream_t stream, int64_t need) {
+                        hipStream_t stream, int64_t need, int32_t *lcp_or_null = nullptr,
+                        int32_t *lcp_flag = nullptr) {
     Tune t;
     SA_TRY(resolve_tuning(tune, &t));
     if (ws_bytes < need)
@@ -593,10 +600,15 @@ static int build_common(const uint8_t *text, int64_t n, const int64_t *set_off_h
     }
     int rounds = 0;
     SA_TRY(B.run(use_graph, &rounds));
-    if (isa_or_null) {
+    if (isa_or_null || lcp_or_null) {
         unsigned grid = unsigned((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
         hipLaunchKernelGGL(k_strip, dim3(grid), dim3(256), 0, stream, B.rank, uint32_t(n));
         SA_HIP(hipGetLastError());
+    }
+    if (lcp_or_null) {
+        if (n_sets < 1 || !B.L.lcp_ws) return fail(SA_ERR_INVALID, "LCP output needs a batched build");
+        SA_TRY(lcp_run(text, n, sa, reinterpret_cast<const int32_t *>(B.rank), lcp_or_null,
+                       B.L.lcp_ws, B.L.lcp_ws_bytes, stream, lcp_flag));
     }
     if (rounds_h) *rounds_h = rounds;
     return SA_OK;
@@ -679,9 +691,10 @@ extern "C" int64_t sa_build_batched_ws_bytes(int64_t n, int32_t n_sets, const in
 }
 
 static int sa_build_batched_impl(const uint8_t *text, int64_t n, const int64_t *set_off_h,
-                                int32_t n_sets, int32_t *sa, int32_t *isa_or_null, void *ws,
-                                int64_t ws_bytes, const sa_tuning *tune, int32_t use_graph,
-                                int32_t *rounds_h, hipStream_t stream) {
+                                int32_t n_sets, int32_t *sa, int32_t *isa_or_null,
+                                int32_t *lcp_or_null, void *ws, int64_t ws_bytes,
+                                const sa_tuning *tune, int32_t use_graph, int32_t *rounds_h,
+                                hipStream_t stream) {
     if (!text || !sa || !ws || !set_off_h) return fail(SA_ERR_INVALID, "sa_build_batched: NULL pointer");
     if (n < 1 || n_sets < 1) return fail(SA_ERR_INVALID, "sa_build_batched: need n >= 1 and n_sets >= 1");
     if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_build_batched: n >= 2^31-2");
@@ -706,7 +719,8 @@ static int sa_build_batched_impl(const uint8_t *text, int64_t n, const int64_t *
         int32_t r = 0;
         SA_TRY(build_common(text + base, len, local.data(), s1 - s0, sa + base,
                             isa_or_null ? isa_or_null + base : nullptr, ws, ws_bytes, &inner,
-                            use_graph != 0, &r, stream, need));
+                            use_graph != 0, &r, stream, need,
+                            lcp_or_null ? lcp_or_null + base : nullptr, lcp_or_null));
         if (base > 0) {
             hipLaunchKernelGGL(k_add_offset, dim3(unsigned((len + 255) / 256)), dim3(256), 0, stream,
                                sa + base, isa_or_null ? isa_or_null + base : nullptr, len,
@@ -727,8 +741,20 @@ extern "C" int sa_build(const uint8_t *text, int64_t n, int32_t *sa, int32_t *is
 }
 
 extern "C" int sa_build_batched(const uint8_t *text, int64_t n, const int64_t *set_off_h,
-                                int32_t n_sets, int32_t *sa, int32_t *isa_or_null, void *ws,
-                                int64_t ws_bytes, const sa_tuning *tune, int32_t use_graph,
-                                int32_t *rounds_h, hipStream_t stream) {
-    return guard<int>([&] { return sa_build_batched_impl(text, n, set_off_h, n_sets, sa, isa_or_null, ws, ws_bytes, tune, use_graph, rounds_h, stream); });
+                                int32_t n_sets, int32_t *sa, int32_t *isa_or_null,
+                                int32_t *lcp_or_null, void *ws, int64_t ws_bytes,
+                                const sa_tuning *tune, int32_t use_graph, int32_t *rounds_h,
+                                hipStream_t stream) {
+    return guard<int>([&] { return sa_build_batched_impl(text, n, set_off_h, n_sets, sa, isa_or_null, lcp_or_null, ws, ws_bytes, tune, use_graph, rounds_h, stream); });
+}
+
+// One workspace for sa_build, sa_lcp and sa_overlaps (up to n candidate matches).
+extern "C" int64_t sa_workspace_bytes(int64_t n, int64_t n_reads_upper) {
+    if (n < 1) return -1;
+    const int64_t m = n_reads_upper <= 0 || n_reads_upper > n ? n : n_reads_upper;
+    const int64_t b = sa_build_ws_bytes(n, nullptr);
+    const int64_t l = sa_lcp_ws_bytes(n);
+    const int64_t o = sa_overlaps_ws_bytes(n, m, n);
+    int64_t need = b > l ? b : l;
+    return need > o ? need : o;
 }

@@ -250,12 +250,13 @@ static int run_batch(asm_server *S, std::vector<Job *> &js, Batch *B, hipStream_
     int64_t scr_bytes = batch_scratch_bytes(n, nj);
     char *scr = S->arena.ptr(scratch[0]);
     int32_t rounds = 0;
-    if (S->mode == 1 && nj == 1)
+    if (S->mode == 1 && nj == 1) {
         SA_TRY(sa_build(text, n, B->sa, B->isa, scr, scr_bytes, nullptr, &rounds, s));
-    else
-        SA_TRY(sa_build_batched(text, n, off.data(), nj, B->sa, B->isa, scr, scr_bytes, nullptr, 0,
-                                &rounds, s));
-    SA_TRY(sa_lcp(text, n, B->sa, B->isa, B->lcp, scr, scr_bytes, s));
+        SA_TRY(sa_lcp(text, n, B->sa, B->isa, B->lcp, scr, scr_bytes, s));
+    } else {
+        SA_TRY(sa_build_batched(text, n, off.data(), nj, B->sa, B->isa, B->lcp, scr, scr_bytes,
+                                nullptr, 0, &rounds, s));
+    }
     // overlaps (one min_len per batch; admission keeps it uniform), into scratch rows first
     int64_t cap = n / 32 + 4096;
     int64_t n_out = 0, need = 0;
@@ -316,10 +317,23 @@ static int run_batch(asm_server *S, std::vector<Job *> &js, Batch *B, hipStream_
     return SA_OK;
 }
 
+// A job that ends without running (no room for it even in an empty arena): its status, time
+// and count are final and its host text is dropped.  Caller holds the lock.
+static void finish_unrun_locked(asm_server *S, Job *j, int status) {
+    j->status = status;
+    j->t_done = now_s(S);
+    j->batch = nullptr;
+    std::vector<uint8_t>().swap(j->text);
+    j->borrowed = nullptr;
+    ++S->jobs_done;
+}
+
 static void worker_main(asm_server *S) {
     hipSetDevice(S->device);
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+    const int full_limit = S->mode == 1 ? 1 : S->max_jobs;
+    int limit = full_limit;  // jobs this worker lays into its next batch
     while (true) {
         std::vector<Job *> js;
         Batch *B = nullptr;
@@ -330,7 +344,6 @@ static void worker_main(asm_server *S) {
             if (S->stop && S->queue.empty()) break;
             // admission: FIFO with bounded look-ahead, one min_len per batch
             int64_t chars = 0;
-            const int max_jobs = S->mode == 1 ? 1 : S->max_jobs;
             int looked = 0;
             for (auto it = S->queue.begin(); it != S->queue.end() && looked < S->lookahead;) {
                 Job *j = *it;
@@ -342,7 +355,7 @@ static void worker_main(asm_server *S) {
                 js.push_back(j);
                 chars += j->n;
                 it = S->queue.erase(it);
-                if (int(js.size()) >= max_jobs) break;
+                if (int(js.size()) >= limit) break;
             }
             if (js.empty()) continue;
             int64_t keep = 0;
@@ -351,22 +364,29 @@ static void worker_main(asm_server *S) {
             const int64_t scr = mem >= 0 ? S->arena.alloc(batch_scratch_bytes(chars, int(js.size()))) : -1;
             if (mem < 0 || scr < 0) {
                 if (mem >= 0) S->arena.release(mem);
-                if (S->concurrent_now == 0 && js.size() == 1) {
-                    // nothing in flight will free memory and the job alone does not fit
-                    js[0]->status = SA_ERR_NOMEM;
-                    js[0]->t_done = now_s(S);
+                // put back, keeping FIFO order
+                for (auto r = js.rbegin(); r != js.rend(); ++r) S->queue.push_front(*r);
+                if (js.size() > 1) {
+                    // try again at once with half the jobs; the full batch size comes back with
+                    // the next admission that fits
+                    limit = int(js.size()) / 2;
+                    continue;
+                }
+                if (S->arena.used() == 0 || (S->stop && S->concurrent_now == 0)) {
+                    // one job that finds no room even in an empty arena (or, while the server
+                    // shuts down, no room that any batch still running will free)
+                    Job *j = S->queue.front();
+                    S->queue.pop_front();
+                    finish_unrun_locked(S, j, SA_ERR_NOMEM);
                     S->cv.notify_all();
                     continue;
                 }
-                // put back (keeping FIFO order), retry with fewer jobs or after a batch ends
-                for (auto r = js.rbegin(); r != js.rend(); ++r) S->queue.push_front(*r);
-                if (S->concurrent_now == 0) {
-                    S->max_jobs = S->max_jobs > 1 ? S->max_jobs / 2 : 1;
-                } else {
-                    S->cv.wait_for(lk, std::chrono::milliseconds(2));
-                }
+                // the memory is held by batches in flight or by finished jobs the caller has not
+                // released yet: wait for a batch to end or a release (both notify)
+                S->cv.wait_for(lk, std::chrono::milliseconds(5));
                 continue;
             }
+            limit = full_limit;
             B = new Batch;
             B->mem_off = mem;
             B->refs = int(js.size());
@@ -397,6 +417,9 @@ static void worker_main(asm_server *S) {
             ++k;
         }
         int rc = js.empty() ? SA_OK : run_batch(S, js, B, s, scratch);
+        // A batch that failed part-way may still have kernels in flight on this stream (sa_lcp
+        // does not synchronise): they must finish before its arena regions go to anyone else.
+        if (rc != SA_OK) (void)hipStreamSynchronize(s);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             --S->concurrent_now;

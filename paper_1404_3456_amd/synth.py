@@ -227,16 +227,28 @@ def serving_jobs(index: int = 3, n_jobs: int = 2000, rate_per_s: float = 1.0,
     """Poisson stream of assembly jobs: genome length log-uniform [g_lo, g_hi], reads uniform
     150..min(800, G), 8x coverage, 0.5 % substitutions, overlaps >= 40.  Returns
     (arrival_times_s, [ReadSet, ...])."""
+    arrivals, sizes = serving_plan(index, n_jobs, rate_per_s, g_lo, g_hi)
+    return arrivals, [serving_job(index, j, g) for j, g in enumerate(sizes)]
+
+
+def serving_plan(index: int = 3, n_jobs: int = 2000, rate_per_s: float = 1.0,
+                 g_lo: int = 1_000, g_hi: int = 5_000_000):
+    """Arrival times and genome lengths of the serving stream (the draws serving_jobs makes
+    before generating each job's reads)."""
     (r_top,) = _rngs(index, 1)
     gaps = r_top.exponential(1.0 / rate_per_s, size=n_jobs)
     arrivals = np.cumsum(gaps) - gaps[0]
-    jobs = []
-    for j in range(n_jobs):
-        rg, rs, re = [np.random.Generator(np.random.PCG64(c))
-                      for c in np.random.SeedSequence(SEED_BASE + index, spawn_key=(j,)).spawn(3)]
-        g = int(round(math.exp(r_top.uniform(math.log(g_lo), math.log(g_hi)))))
-        jobs.append(_variable_set(rg, rs, re, g, 150, 800, 8.0, 0.005, 40, f"job{j}"))
-    return arrivals, jobs
+    sizes = [int(round(math.exp(r_top.uniform(math.log(g_lo), math.log(g_hi)))))
+             for _ in range(n_jobs)]
+    return arrivals, sizes
+
+
+def serving_job(index: int, j: int, g: int) -> ReadSet:
+    """Job j of the serving stream with genome length g: its reads depend only on (index, j,
+    g), so jobs can be generated independently (and in parallel)."""
+    rg, rs, re = [np.random.Generator(np.random.PCG64(c))
+                  for c in np.random.SeedSequence(SEED_BASE + index, spawn_key=(j,)).spawn(3)]
+    return _variable_set(rg, rs, re, g, 150, 800, 8.0, 0.005, 40, f"job{j}")
 
 
 def random_dna_reads(seed: int, m: int, len_lo: int, len_hi: int, alphabet: bytes = b"ACGT",

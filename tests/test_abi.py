@@ -134,3 +134,31 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_abi, "_LIB", str(tmp_path / "libsaasm.so"))
     with pytest.raises(ImportError):
         _abi.load()
+
+
+def test_one_workspace_covers_the_path():
+    """sa_workspace_bytes is at least what each call of the path asks for: sa_build (default
+    tuning), sa_lcp (both LCP forms) and sa_overlaps with up to n candidate matches."""
+    for n, m in ((1, 1), (100, 3), (80_400, 400), (50_100_000, 100_000), ((1 << 31) - 3, 2_147_484)):
+        w = _abi.sa_workspace_bytes(n, m)
+        assert w >= _abi.sa_build_ws_bytes(n), n
+        assert w >= _abi.sa_lcp_ws_bytes(n), n
+        assert w >= _abi.sa_overlaps_ws_bytes(n, m, n), n
+        assert w >= _abi.sa_overlaps_ws_bytes(n, m, 0), n
+        assert _abi.sa_workspace_bytes(n, 0) >= w  # no read bound: as if every byte were a read
+    assert _abi.sa_workspace_bytes(0, 0) == -1
+
+
+def test_lcp_status_and_batched_lcp_host_checks():
+    lib = _abi.load()
+    dummy = ctypes.c_void_p(16)
+    assert lib.sa_lcp_status(None, None) == _abi.SA_ERR_INVALID
+    off = np.array([0, 50, 100], dtype=np.int64)
+    P = ctypes.c_void_p
+    # NULL text; then a workspace too small; the LCP output pointer is optional
+    assert lib.sa_build_batched(None, 100, off.ctypes.data_as(P), 2, dummy, None, None, dummy,
+                                1 << 20, None, 0, None, None) == _abi.SA_ERR_INVALID
+    assert lib.sa_build_batched(dummy, 100, off.ctypes.data_as(P), 2, dummy, None, dummy, dummy,
+                                16, None, 0, None, None) == _abi.SA_ERR_NOMEM
+    # the batched workspace holds the LCP's room as well
+    assert _abi.sa_build_batched_ws_bytes(1_000_000, 2) > _abi.sa_build_ws_bytes(1_000_000)

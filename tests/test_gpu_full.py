@@ -1,6 +1,9 @@
-"""Parity at full workload sizes, in the launch configuration the benchmark times: outputs the
-oracle can check at any size (permutation, sampled adjacent order and LCP, the Kasai property)
-and the complete overlap set from the oracle's exact seed-and-verify search."""
+"""Parity at full workload sizes, in the launch configuration the benchmark times.  The suffix
+array and LCP are checked element by element: the SA is a permutation and every adjacent pair
+of suffixes ascends with its LCP entry equal to the direct common prefix (oracle.check_all over
+all n - 1 pairs), which together are the definition -- a permutation whose neighbours all ascend
+is the sorted order.  Overlaps are compared whole with the oracle's exact seed-and-verify
+search (or, at the largest size, with the exact positional truth of error-free reads)."""
 import numpy as np
 import pytest
 
@@ -19,7 +22,7 @@ def pkg():
     return p
 
 
-def full_check(pkg, r, samples=400_000):
+def full_check(pkg, r):
     print(f"full-size case {r.name}: n={r.n}", flush=True)
     t = torch.from_numpy(r.text).cuda()
     sa, isa = pkg.sa_build(t)
@@ -30,10 +33,8 @@ def full_check(pkg, r, samples=400_000):
     del t
     checks.assert_sa_basic(r.text, sa)
     assert np.array_equal(isa[sa], np.arange(r.n, dtype=np.int32))
-    rng = np.random.default_rng(r.n)
-    idx = np.unique(np.concatenate([rng.integers(1, r.n, size=samples), [1, r.n - 1]]))
-    bad, first = oracle.check_adjacent(r.text, sa, lcp, idx)
-    assert bad == 0, f"first bad adjacent pair at {first}"
+    bad, first = oracle.check_all(r.text, sa, lcp)
+    assert bad == 0, f"{bad} bad adjacent pairs, the first at {first}"
     assert lcp[0] == 0
     checks.assert_kasai_property(r.text, sa, lcp)
     want = oracle.overlaps(r.text, r.min_len)
@@ -47,7 +48,7 @@ def test_full_plain_large(pkg):
 
 
 def test_full_repeat_stress(pkg):
-    rows = full_check(pkg, synth.repeat_stress(), samples=200_000)
+    rows = full_check(pkg, synth.repeat_stress())
     assert rows > 0
 
 
@@ -85,9 +86,10 @@ def max_size_text():
 
 def test_full_max_size(pkg):
     """n = 2^31 - 3 (positions, ranks and counts at the edge of 32 bits): SA, ISA, LCP and
-    overlaps through the C ABI, and the skew construction's SA.  SA and LCP: permutation, the
-    oracle's sampled adjacent order and LCP; the skew SA equal to the checked one.  Overlaps: the exact positional truth of error-free reads from a random genome,
-    and direct string checks of sampled rows."""
+    overlaps through the C ABI, and the skew construction's SA.  SA and LCP: permutation and
+    every adjacent pair's order and LCP; the skew SA equal to the checked one.  Overlaps: the
+    exact positional truth of error-free reads from a random genome, and direct string checks
+    of sampled rows."""
     text, starts, lengths = max_size_text()
     n = text.size
     print(f"max-size case: n={n}", flush=True)
@@ -109,11 +111,10 @@ def test_full_max_size(pkg):
     assert np.array_equal(isa[sa], np.arange(n, dtype=np.int32))
     del isa
     assert same_dc3, "the skew construction differs from the doubling one"
-    rng = np.random.default_rng(7)
-    idx = np.unique(np.concatenate([rng.integers(1, n, size=200_000), [1, n - 1]]))
-    bad, first = oracle.check_adjacent(text, sa, lcp, idx)
-    assert bad == 0, f"first bad adjacent pair at {first}"
+    bad, first = oracle.check_all(text, sa, lcp)
+    assert bad == 0, f"{bad} bad adjacent pairs, the first at {first}"
     assert lcp[0] == 0
+    rng = np.random.default_rng(7)
     del sa, lcp
     want = checks.positional_overlaps_ragged(starts, lengths, 100)
     assert np.array_equal(ovl, want)
@@ -124,10 +125,10 @@ def test_full_max_size(pkg):
 
 def test_full_batched_256(pkg):
     """The 256-set batched workload (1.43 G characters) in one build, as the benchmark runs it:
-    every set's block of the SA is a permutation of its own positions, ISA is the inverse, the
-    oracle's sampled adjacent order and LCP hold inside every set with LCP 0 at set starts, no
-    overlap row pairs reads of different sets, and the rows of every eighth set equal the
-    oracle's overlaps of that set alone."""
+    every set's block of the SA is a permutation of its own positions, ISA is the inverse,
+    every adjacent pair inside every set ascends with its LCP equal to the direct common prefix
+    (LCP 0 at set starts), and every set's overlap rows equal the oracle's overlaps of that set
+    alone."""
     sets = synth.batched_sets()
     off = np.concatenate([[0], np.cumsum([s.text.size for s in sets])]).astype(np.int64)
     cat = np.concatenate([s.text for s in sets])
@@ -150,20 +151,18 @@ def test_full_batched_256(pkg):
         seps = checks.separators(sets[s].text) + lo
         assert np.array_equal(blk[: seps.size], seps), f"set {s}: separators first, in order"
         assert lcp[lo] == 0, f"set {s} first LCP"
-    starts = set(off[:-1].tolist())
-    rng = np.random.default_rng(n)
-    idx = np.unique(rng.integers(1, n, size=400_000))
-    idx = idx[~np.isin(idx, list(starts))]
-    bad, first = oracle.check_adjacent(cat, sa, lcp, idx)
-    assert bad == 0, f"first bad adjacent pair at {first}"
+    for s in range(len(sets)):
+        lo, hi = int(off[s]), int(off[s + 1])
+        bad, first = oracle.check_all(cat, sa, lcp, lo=lo + 1, hi=hi)
+        assert bad == 0, f"set {s}: {bad} bad adjacent pairs, the first at {first}"
     del sa, lcp
     reads = np.array([0] + [int((s.text == ord("$")).sum()) for s in sets]).cumsum()
     set_of_read = np.repeat(np.arange(len(sets)), np.diff(reads))
     assert np.array_equal(set_of_read[ovl[:, 0]], set_of_read[ovl[:, 1]]), "rows across sets"
-    for s in range(0, len(sets), 8):
+    for s in range(len(sets)):
         a0, a1 = np.searchsorted(ovl[:, 0], [reads[s], reads[s + 1]])
         want = oracle.overlaps(sets[s].text, 40).astype(np.int64)
         want[:, :2] += reads[s]
         assert np.array_equal(ovl[a0:a1].astype(np.int64), want), f"set {s} overlaps"
-    print(f"full-size batched: {ovl.shape[0]} rows, {len(range(0, len(sets), 8))} sets against "
-          f"the oracle", flush=True)
+    print(f"full-size batched: {ovl.shape[0]} rows, all {len(sets)} sets against the oracle",
+          flush=True)

@@ -139,8 +139,12 @@ def test_tiny_exhaustive(lib):
     rng = np.random.default_rng(5)
     texts += [t for t in tiny_dna_texts(6) if rng.random() < 0.05]
     for t in texts:
-        sa, isa = run_sa(lib, t)
-        assert np.array_equal(sa, oracle.suffix_array(t)), t.tobytes()
+        sa, isa, lcp, ovl = run_all(lib, t, 1)
+        want = oracle.suffix_array(t)
+        assert np.array_equal(sa, want), t.tobytes()
+        assert np.array_equal(isa[sa], np.arange(t.size)), t.tobytes()
+        assert np.array_equal(lcp, oracle.lcp_array(t, want)), t.tobytes()
+        assert np.array_equal(ovl.reshape(-1, 3), oracle.overlaps_brute(t, 1)), t.tobytes()
 
 
 EDGE = {
@@ -278,6 +282,56 @@ def test_batched_parity(lib, seed, n_sets, use_graph):
         reads_before += int((txt == ord("$")).sum())
     want = np.concatenate(rows) if rows else np.zeros((0, 3))
     assert np.array_equal(ovl.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("seg_pack,use_graph", [(0, False), (0, True), (20_000, False)])
+def test_batched_lcp_output(lib, seg_pack, use_graph):
+    """The LCP computed inside sa_build_batched (one build, or several packed builds whose LCP
+    lands at their offsets) equals sa_lcp over the concatenation and the oracle per set."""
+    texts, off, cat = _batched_case(21, 40)
+    t = dev(cat)
+    tu = {"seg_pack": seg_pack} if seg_pack else None
+    sa, isa, lcp = lib.sa_build_batched(t, off, tuning=tu, use_graph=use_graph, lcp=True)
+    lcp2 = lib.sa_lcp(t, sa, isa)
+    sa, lcp, lcp2 = sa.cpu().numpy(), lcp.cpu().numpy(), lcp2.cpu().numpy()
+    assert np.array_equal(lcp, lcp2)
+    for s, txt in enumerate(texts):
+        lo, hi = off[s], off[s + 1]
+        want_sa = oracle.suffix_array(txt)
+        assert np.array_equal(sa[lo:hi] - lo, want_sa), f"set {s}"
+        assert np.array_equal(lcp[lo:hi], oracle.lcp_array(txt, want_sa)), f"set {s} lcp"
+
+
+def test_lcp_reports_device_failures(lib):
+    """sa_lcp is asynchronous: a bad byte it meets is left in lcp[0] as the negative status,
+    sa_lcp_status raises it, and sa_overlaps refuses an LCP array that carries it."""
+    good = synth.genome_reads(5, 3000, 60, 80, err=0.01)
+    t = dev(good)
+    sa, isa = lib.sa_build(t)
+    bad = good.copy()
+    bad[100] = ord("N")
+    lcp = lib.sa_lcp(dev(bad), sa, isa)
+    assert int(lcp[0].item()) == lib.SA_ERR_ALPHABET
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_lcp_status(lcp)
+    assert e.value.code == lib.SA_ERR_ALPHABET
+    with pytest.raises(lib.SaasmError) as e:
+        lib.sa_overlaps(t, sa, isa, lcp, 20)
+    assert e.value.code == lib.SA_ERR_ALPHABET
+    ok = lib.sa_lcp(t, sa, isa, check=True)  # the same call on the good text reports nothing
+    assert int(ok[0].item()) == 0
+
+
+def test_one_workspace_for_the_path(lib):
+    """sa_build, sa_lcp and sa_overlaps share one workspace of sa_workspace_bytes(n) bytes."""
+    t = synth.genome_reads(31, 40_000, 1500, 200, err=0.005)
+    need = lib.sa_workspace_bytes(t.size, int((t == ord("$")).sum()))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    sa, isa, lcp, ovl = lib.sa_path(dev(t), 25, ws=ws)
+    want = oracle.suffix_array(t)
+    assert np.array_equal(sa.cpu().numpy(), want)
+    assert np.array_equal(lcp.cpu().numpy(), oracle.lcp_array(t, want))
+    assert np.array_equal(ovl.cpu().numpy(), oracle.overlaps(t, 25))
 
 
 def test_batched_graph_repeated_with_eager_work_between(lib):

@@ -416,3 +416,62 @@ def test_planted_mistake_is_caught(name, tmp_path):
         assert ok, "unmutated oracle must pass its pins"
     else:
         assert not ok, f"planted mistake {name} was not caught by any pin"
+
+
+# ---- the merge path of the oracle's parallel sort, and the exhaustive full-size check -------
+
+def _merge_path_texts():
+    return [
+        synth.random_dna_reads(77, 90, 20, 120, allow_empty=True),
+        synth.genome_reads(78, 1500, 60, 90, err=0.0),     # heavy overlap: long equal prefixes
+        synth.genome_reads(79, 900, 40, 150, err=0.01, alphabet_size=2),
+        np.frombuffer(b"A" * 3000 + b"$" + b"AC" * 1000 + b"$" + b"A" * 2500 + b"$",
+                      dtype=np.uint8).copy(),
+    ]
+
+
+@pytest.mark.parametrize("nthreads", [2, 3, 8])
+def test_sa_merge_path_vs_brute(nthreads):
+    """Above 4096 characters the oracle sorts per-thread chunks and merges them; that order
+    must still be the literal definition's."""
+    for t in _merge_path_texts():
+        assert t.size > 4096
+        want = np.array(brute.suffix_array(t.tobytes()), dtype=np.int32)
+        assert np.array_equal(oracle.suffix_array(t, nthreads=nthreads), want)
+
+
+def test_check_all_agrees_with_bytewise_check():
+    """check_all (whole words skipped while equal and separator-free) fails exactly the
+    indices the byte-by-byte check_adjacent fails, on correct arrays and on planted errors:
+    swapped neighbours, a moved entry, an LCP off by one either way, a repeated entry."""
+    rng = np.random.default_rng(3)
+    for t in _merge_path_texts() + [np.frombuffer(s, dtype=np.uint8).copy() for s in TINY[::97]]:
+        n = t.size
+        sa = oracle.suffix_array(t)
+        lcp = oracle.lcp_array(t, sa)
+        every = np.arange(1, n, dtype=np.int64)
+        assert oracle.check_all(t, sa, lcp) == (0, -1)
+        assert oracle.check_adjacent(t, sa, lcp, every) == (0, -1)
+        if n < 3:
+            continue
+        for trial in range(6):
+            s2, l2 = sa.copy(), lcp.copy()
+            i = int(rng.integers(1, n - 1))
+            if trial == 0:
+                s2[i], s2[i + 1] = s2[i + 1], s2[i]
+            elif trial == 1:
+                j = int(rng.integers(0, n))
+                s2 = np.insert(np.delete(s2, i), j, s2[i])
+            elif trial == 2:
+                l2[i] += 1
+            elif trial == 3:
+                l2[i] -= 1
+            elif trial == 4:
+                s2[i] = s2[i - 1]
+            else:
+                s2 = s2[::-1].copy()
+            got = oracle.check_all(t, s2, l2)
+            want = oracle.check_adjacent(t, s2, l2, every)
+            assert got == want, (trial, got, want)
+            if trial != 1 or not np.array_equal(s2, sa):
+                assert got[0] > 0 or (trial == 1 and np.array_equal(s2, sa)), trial
