@@ -260,6 +260,30 @@ int sa_reconstruct(const uint8_t *text_h, int64_t n, const int32_t *sa_h, const 
                    const int32_t *lcp_h, int32_t *order_h, uint8_t *rs_h, int64_t rs_cap,
                    int64_t *rs_len_h, int64_t max_steps);
 
+/* sa_overlap_path: HOST function.  Sec. III reads a reconstruction off a weighted directed
+ * graph: one vertex per fragment, an edge a -> b weighted by the overlap length l(a, b), and the
+ * superstring obtained by merging the fragments along a Hamiltonian path of maximal total
+ * weight (each next fragment contributes what lies past its overlap with the one before).
+ *   text_h, n     the fragments, each closed by '$' (host memory; any bytes besides '$')
+ *   rows_h, r     [r][3] host rows (a, b, l): the edges, e.g. sa_overlaps' output copied to the
+ *                 host; any order; pairs without a row weigh 0
+ *   exact_max_m   m <= exact_max_m (at most 20): exact search, dynamic programming over subsets
+ *                 of fragments (2^m * m^2 steps, 9 * 2^m * m bytes of host memory); among paths
+ *                 of equal weight the one found first (subsets in increasing order, fragments in
+ *                 increasing id) ending at the smallest id.  Larger m: the greedy rule -- edges
+ *                 by weight (heaviest first, then by a, then by b), an edge kept when a has no
+ *                 successor yet, b no predecessor and the two are not in one chain already; the
+ *                 chains laid end to end in order of their first fragment.
+ *   order_h       [m] out: fragment ids along the path
+ *   weight_h      out: the path's total weight
+ *   rs_h          [rs_cap] out, may be NULL when rs_cap is 0: the merged superstring
+ *   rs_len_h      out: its length
+ * Returns SA_ERR_INVALID for rows that name fragments out of range, a == b, or a length above
+ * either fragment's; SA_ERR_CAPACITY (order, weight and *rs_len_h set) when rs_cap is too small. */
+int sa_overlap_path(const uint8_t *text_h, int64_t n, const int32_t *rows_h, int64_t r,
+                    int32_t exact_max_m, int32_t *order_h, int64_t *weight_h, uint8_t *rs_h,
+                    int64_t rs_cap, int64_t *rs_len_h);
+
 /* ---------------------------------------------------------------------------------------- */
 /* Suffix-prefix overlaps between fragments (Sec. III: a fragment is 'fir' when it is a prefix */
 /* of another; the weighted overlap graph's edge weights are overlap lengths; Sec. IV: the     */

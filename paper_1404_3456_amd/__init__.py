@@ -36,6 +36,7 @@ from ._abi import (  # noqa: F401
     sa_lcp_ws_bytes,
     sa_lookup,
     sa_lookup_ws_bytes,
+    sa_overlap_path,
     sa_reconstruct,
     sa_reconstruct_host,
     sa_revcomp_text,

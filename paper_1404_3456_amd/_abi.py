@@ -85,6 +85,7 @@ def load():
         "sa_lcp_ws_bytes": ([I64], I64),
         "sa_lookup_ws_bytes": ([I64, I64], I64),
         "sa_reconstruct": ([P, I64, P, P, P, P, P, I64, P, I64], ctypes.c_int),
+        "sa_overlap_path": ([P, I64, P, I64, I32, P, P, P, I64, P], ctypes.c_int),
         "sa_revcomp_text": ([P, I64, P, P, P, I64, P], ctypes.c_int),
         "sa_strand_rows_ws_bytes": ([I64, I64], I64),
         "sa_strand_rows": ([P, I64, I64, P, I64, P, P, I64, P], ctypes.c_int),
@@ -413,6 +414,27 @@ def sa_reconstruct_host(text, sa, isa, lcp, max_steps: int = 10 ** 7):
         return None
     _check(rc)
     return bytes(rs[: rs_len.value]), order[:m].tolist()
+
+
+def sa_overlap_path(text, rows, exact_max_m: int = 16):
+    """Maximal-weight Hamiltonian path through the weighted overlap graph (host search over
+    host arrays): (order list, total weight, superstring bytes).  `text` holds the fragments
+    ('$'-closed), `rows` the (r, 3) overlap rows (numpy, or a tensor copied to the host)."""
+    import numpy as np
+    t = np.ascontiguousarray(text, dtype=np.uint8)
+    if hasattr(rows, "cpu"):
+        rows = rows.cpu().numpy()
+    rw = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1, 3))
+    m = int((t == ord("$")).sum())
+    order = np.zeros(max(m, 1), dtype=np.int32)
+    weight = ctypes.c_int64(0)
+    rs = np.zeros(max(t.size, 1), dtype=np.uint8)
+    rs_len = ctypes.c_int64(0)
+    P = ctypes.c_void_p
+    _check(load().sa_overlap_path(t.ctypes.data_as(P), t.size, rw.ctypes.data_as(P), rw.shape[0],
+                                  int(exact_max_m), order.ctypes.data_as(P), ctypes.byref(weight),
+                                  rs.ctypes.data_as(P), rs.size, ctypes.byref(rs_len)))
+    return order[:m].tolist(), int(weight.value), bytes(rs[: rs_len.value])
 
 
 def to_host(*tensors):

@@ -554,3 +554,40 @@ def test_build_switches_from_radix_rounds_to_run_sort(lib, seed):
     first_round = 7 * n * 24.0  # 63-bit first-round keys, 9-bit digits, 24 B per item
     assert radix_bytes > first_round, "no doubling round sorted by radix passes"
     assert runs_bytes > 0, "no doubling round sorted group by group"
+
+
+# ---- the weighted overlap graph's maximal path over GPU-built overlaps (Sec. III) ------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_overlap_path_from_gpu_overlaps(lib, seed):
+    """Seven to nine reads of a short genome: the overlaps built on the GPU, the exact path
+    search over them; its weight is the exhaustive maximum over the oracle's overlaps and the
+    merge along it is the oracle's merge."""
+    from oracle import path as opath
+    m = 7 + seed % 3
+    t = synth.genome_reads(500 + seed, 600, m, 150, err=0.0)
+    sa, isa, lcp, ovl = run_all(lib, t, 10)
+    want = oracle.overlaps(t, 10)
+    assert np.array_equal(ovl.reshape(-1, 3), want)
+    order, weight, rs = lib.sa_overlap_path(t, ovl)
+    w = opath.weights(want)
+    frags = bytes(t).split(b"$")[:-1]
+    assert sorted(order) == list(range(m))
+    assert weight == opath.path_weight(order, w) == opath.best_weight_exhaustive(m, w)
+    assert rs == opath.merge(frags, order, w)
+
+
+def test_overlap_path_greedy_on_small_workload(lib):
+    """The 400-read small workload: the greedy rule over the GPU-built overlaps takes the
+    oracle's steps (same order, weight and superstring)."""
+    from oracle import path as opath
+    r = synth.small_plain()
+    sa, isa, lcp, ovl = run_all(lib, r.text, r.min_len)
+    want = oracle.overlaps(r.text, r.min_len)
+    assert np.array_equal(ovl.reshape(-1, 3), want)
+    order, weight, rs = lib.sa_overlap_path(r.text, ovl, exact_max_m=0)
+    w = opath.weights(want)
+    assert order == opath.greedy_path(r.m, w)
+    assert weight == opath.path_weight(order, w)
+    frags = bytes(r.text).split(b"$")[:-1]
+    assert rs == opath.merge(frags, order, w)
