@@ -64,8 +64,13 @@ def _load():
     return _lib
 
 
-def _threads(nthreads):
+def _threads(nthreads, work=None):
+    """Thread count for one call: the caller's, else OMP_NUM_THREADS (else every core), but one
+    thread for inputs too small to share (a thread team per tiny call costs more than the work,
+    and under several test processes its waiting threads crowd out the others)."""
     if nthreads is None:
+        if work is not None and work < (1 << 16):
+            return 1
         nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return max(1, int(nthreads))
 
@@ -86,7 +91,7 @@ def _ptr(a: np.ndarray):
 def suffix_array(text, nthreads=None) -> np.ndarray:
     t = _text(text)
     sa = np.empty(t.size, dtype=np.int32)
-    rc = _load().oracle_sa(_ptr(t), t.size, _ptr(sa), _threads(nthreads))
+    rc = _load().oracle_sa(_ptr(t), t.size, _ptr(sa), _threads(nthreads, t.size))
     if rc != 0:
         raise RuntimeError(f"oracle_sa failed ({rc})")
     return sa
@@ -96,7 +101,7 @@ def lcp_array(text, sa, nthreads=None) -> np.ndarray:
     t = _text(text)
     sa = np.ascontiguousarray(sa, dtype=np.int32)
     lcp = np.empty(t.size, dtype=np.int32)
-    rc = _load().oracle_lcp(_ptr(t), t.size, _ptr(sa), _ptr(lcp), _threads(nthreads))
+    rc = _load().oracle_lcp(_ptr(t), t.size, _ptr(sa), _ptr(lcp), _threads(nthreads, t.size))
     if rc != 0:
         raise RuntimeError(f"oracle_lcp failed ({rc})")
     return lcp
@@ -104,7 +109,7 @@ def lcp_array(text, sa, nthreads=None) -> np.ndarray:
 
 def _overlaps(fn, text, min_len, nthreads):
     t = _text(text)
-    nt = _threads(nthreads)
+    nt = _threads(nthreads, t.size)
     total = fn(_ptr(t), t.size, int(min_len), None, 0, nt)
     if total < 0:
         raise ValueError("bad text or min_len")
@@ -151,7 +156,7 @@ def check_adjacent(text, sa, lcp, idx, nthreads=None):
         lp = _ptr(lcp)
     first = ctypes.c_int64(-1)
     bad = _load().oracle_check_adjacent(_ptr(t), t.size, _ptr(sa), lp, _ptr(idx), idx.size,
-                                        ctypes.byref(first), _threads(nthreads))
+                                        ctypes.byref(first), _threads(nthreads, idx.size))
     return int(bad), int(first.value)
 
 
@@ -171,7 +176,7 @@ def check_all(text, sa, lcp, lo=1, hi=None, nthreads=None):
     hi = t.size if hi is None else int(hi)
     first = ctypes.c_int64(-1)
     bad = _load().oracle_check_range(_ptr(t), t.size, _ptr(sa), lp, int(lo), hi,
-                                     ctypes.byref(first), _threads(nthreads))
+                                     ctypes.byref(first), _threads(nthreads, hi - int(lo)))
     return int(bad), int(first.value)
 
 
@@ -186,7 +191,7 @@ def lookup(text, patterns, nthreads=None) -> np.ndarray:
     buf = np.frombuffer(b"".join(pats) + b"\0", dtype=np.uint8).copy()
     out = np.zeros((max(len(pats), 1), 2), dtype=np.int64)
     rc = _load().oracle_lookup(_ptr(t), t.size, _ptr(buf), _ptr(off), len(pats), _ptr(out),
-                               _threads(nthreads))
+                               _threads(nthreads, t.size * max(len(pats), 1)))
     if rc != 0:
         raise ValueError("pattern holds a separator, or bad text")
     return out[: len(pats)]
