@@ -39,10 +39,26 @@ class Arena {
         used_ = 0;
         cap_ = bytes;
     }
-    // Returns an offset or -1.  256-byte granularity.
-    int64_t alloc(int64_t bytes) {
+    // Returns an offset or -1.  256-byte granularity.  Scratch that lives for one batch is
+    // taken first-fit from the bottom (high = false); what outlives the batch (results, overlap
+    // rows) last-fit from the top, so blocks held until the client releases them do not split
+    // the free space the next batch's scratch needs.
+    int64_t alloc(int64_t bytes, bool high = false) {
         bytes = (bytes + 255) & ~int64_t(255);
         if (fail_after_ > 0 && --fail_after_ == 0) return -1;  // injected failure (tests)
+        if (high) {
+            for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
+                if (it->second >= bytes) {
+                    const int64_t start = it->first, off = start + it->second - bytes;
+                    it->second -= bytes;
+                    if (it->second == 0) free_.erase(start);
+                    sizes_[off] = bytes;
+                    used_ += bytes;
+                    return off;
+                }
+            }
+            return -1;
+        }
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
                 int64_t off = it->first, len = it->second;
@@ -221,9 +237,9 @@ static bool scan_text(const uint8_t *t, int64_t n, int64_t *m_out) {
     return bad == 0;
 }
 
-static int64_t arena_alloc(asm_server *S, int64_t bytes) {
+static int64_t arena_alloc(asm_server *S, int64_t bytes, bool high = false) {
     std::lock_guard<std::mutex> lk(S->mu);
-    return S->arena.alloc(bytes);
+    return S->arena.alloc(bytes, high);
 }
 
 // Runs one batch on stream s, without the server lock.  scratch: arena offsets to release
@@ -284,7 +300,7 @@ static int run_batch(asm_server *S, std::vector<Job *> &js, Batch *B, hipStream_
         break;
     }
     if (rc != SA_OK) return rc;
-    B->rows_off = arena_alloc(S, (n_out > 0 ? n_out : 1) * 12);
+    B->rows_off = arena_alloc(S, (n_out > 0 ? n_out : 1) * 12, true);
     if (B->rows_off < 0) return fail(SA_ERR_NOMEM, "server: arena full (rows)");
     B->rows = reinterpret_cast<int32_t *>(S->arena.ptr(B->rows_off));
     if (n_out > 0)
@@ -360,7 +376,7 @@ static void worker_main(asm_server *S) {
             if (js.empty()) continue;
             int64_t keep = 0;
             for (Job *j : js) keep += job_keep_bytes(j->n);
-            const int64_t mem = S->arena.alloc(keep);
+            const int64_t mem = S->arena.alloc(keep, true);
             const int64_t scr = mem >= 0 ? S->arena.alloc(batch_scratch_bytes(chars, int(js.size()))) : -1;
             if (mem < 0 || scr < 0) {
                 if (mem >= 0) S->arena.release(mem);

@@ -195,29 +195,41 @@ def test_failure_inside_a_running_batch(pkg):
 
 def test_batching_resumes_after_a_job_too_large_to_share(pkg):
     """The arena holds the large job alone but not with any other: its batch shrinks until it
-    runs alone, then the small jobs behind it are batched again at the full batch size."""
+    runs alone, then the small jobs behind it are batched again at the full batch size.  The
+    client copies every result out and releases it at once; the oracle checks run after all
+    jobs are back."""
     big = synth.genome_reads(901, 300_000, 6000, 500, err=0.005)     # ~3 M characters
-    smalls = [synth.genome_reads(910 + k, 50_000, 1000, 250, err=0.005) for k in range(40)]
-    n = big.size
+    smalls = [synth.genome_reads(910 + k, 20_000, 400, 250, err=0.005) for k in range(40)]
+    n, ns = big.size, smalls[0].size
     # what the server holds for one job: text, SA, ISA, LCP (13 bytes per character) and the
     # batch scratch (the batched build's workspace, which includes the LCP's), plus the
-    # overlap rows; 8 MiB over that leaves no room for a second job (~15 MB more) beside it
+    # overlap rows; 3 MiB over that is less than one small job adds (~5 MB)
     keep = 13 * n + 4 * 256
     scratch = max(pkg.sa_build_batched_ws_bytes(n, 1), pkg.sa_lcp_ws_bytes(n)) + 4096
-    arena = keep + scratch + (n // 32 + 4096) * 12 + (8 << 20)
+    arena = keep + scratch + (n // 32 + 4096) * 12 + (3 << 20)
+    both = 13 * (n + ns) + 2048 + pkg.sa_build_batched_ws_bytes(n + ns, 2) + 4096
+    assert both > arena
+    # 16 small jobs fit beside the large job's results and one earlier batch's results
+    b16 = 16 * (13 * ns + 1024) + pkg.sa_build_batched_ws_bytes(16 * ns, 16) + 4096
+    assert keep + 16 * (13 * ns + 1024) + b16 < arena
+    got, res = [], []
     with pkg.AsmServer(arena, max_jobs_per_batch=16, workers=1) as srv:
         ids = [srv.asm_submit(big, 40)] + [srv.asm_submit(t, 40) for t in smalls]
-        for jid, t in zip(ids, [big] + smalls):
+        for jid in ids:
             r = wait(srv, jid, timeout=300.0)
             assert r["status"] == 0
-            sa, isa, lcp, ovl = host(r)
-            want = oracle.suffix_array(t)
-            assert np.array_equal(sa, want)
-            assert np.array_equal(lcp, oracle.lcp_array(t, want))
-            assert np.array_equal(ovl, oracle.overlaps(t, 40))
+            got.append(host(r))
+            res.append(r)
             srv.asm_release(jid)
         st = srv.asm_server_stats()
-        assert st["jobs_done"] == 41 and st["arena_used"] == 0
-        # the large job alone, then the 40 small ones batched again (8 or 16 per batch: the
-        # arena holds 8 of them at once); one job per batch would make 41
-        assert st["batches"] <= 1 + 40 // 8, st
+    assert st["jobs_done"] == 41 and st["arena_used"] == 0
+    # the large job ran alone: every small job was admitted after it finished
+    assert min(r["t_admit"] for r in res[1:]) >= res[0]["t_done"]
+    # then the small ones shared batches again (16 at a time: 3 batches; one job per batch
+    # would make 41)
+    assert st["batches"] <= 1 + 40 // 8, st
+    for (sa, isa, lcp, ovl), t in zip(got, [big] + smalls):
+        want = oracle.suffix_array(t)
+        assert np.array_equal(sa, want)
+        assert np.array_equal(lcp, oracle.lcp_array(t, want))
+        assert np.array_equal(ovl, oracle.overlaps(t, 40))
