@@ -121,15 +121,15 @@ int64_t timing_round_begin() {
     return t_tag;
 }
 
-void timing_round_items(int64_t tag, int64_t items, int mode) {
+void timing_round_items(int64_t tag, int64_t items, int64_t big_items) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &p : g_pending) {
         if (p.tag != tag) continue;
         // an empty round still launched its kernels (they exit at once): timed, no bytes; so
-        // are the kernels of the sort mode the round did not use
-        const bool used = p.mode == kModeAny || p.mode == mode;
-        p.bytes = items <= 0 || !used ? 0.0 : p.bytes + p.per_item * double(items);
-        p.items = items <= 0 || !used ? 0.0 : double(items);
+        // are the radix-pass kernels of a round without large groups
+        const int64_t k = p.mode == kModeRadix ? big_items : items;
+        p.bytes = k <= 0 ? 0.0 : p.bytes + p.per_item * double(k);
+        p.items = k <= 0 ? 0.0 : double(k);
         p.tag = -1;
     }
 }

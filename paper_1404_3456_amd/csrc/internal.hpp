@@ -96,11 +96,12 @@ struct TimedScope {
     void finish();
 };
 int64_t timing_round_begin();                       // new tag for the calling thread's round
-// item count of that round (0: no bytes) and how it sorted (kModeRadix or kModeRuns)
-void timing_round_items(int64_t tag, int64_t items, int mode);
+// Units of work of that round: scopes opened in kModeRadix count the items of its large
+// groups (sorted by radix passes), the others every active item (0: no bytes).
+void timing_round_items(int64_t tag, int64_t items, int64_t big_items);
 constexpr int kModeAny = 0, kModeRadix = 1, kModeRuns = 2;
-// Scopes opened by the calling thread from now on only take their round's bytes when the
-// round sorted in this mode (kModeAny: always).
+// The unit count that scopes opened by the calling thread from now on take from their round
+// (kModeRadix: the large groups' items; otherwise all active items).
 void timing_scope_mode(int mode);
 void timing_flush();  // resolve pending events (waits for them)
 void timing_poll();   // resolve only the pending events that have already completed
@@ -168,18 +169,25 @@ constexpr int kStH = 3;        // prefix length the groups are sorted by
 constexpr int kStRounds = 4;   // rounds completed
 constexpr int kStNext = 5;     // active count produced by the round's rank update
 constexpr int kStBig = 6;      // 1: some group entering the round has more than kRunMax members
-constexpr int kStRadixN = 7;   // items the round sorts by radix passes (kStActive or 0)
+constexpr int kStRadixN = 7;   // items of large groups the round sorts by radix passes
 constexpr int kStBigNext = 8;  // set by the rank update for the next round
-constexpr int kStRunsN = 9;    // items the round sorts run by run in LDS (kStActive or 0)
+constexpr int kStBigLast = 9;  // kStRadixN of the round that ended (read back for timing)
+constexpr int kStWords = 16;   // state words the host reads back
 constexpr int kRunMax = 32;    // largest group the run sort handles
 
 // key builders (fused with the histogram of the sort that follows)
 int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int h0,
                 const int64_t *set_off_dev, int n_sets, int key_bits, const SortBufs &b, int cur,
                 const Tune &t, hipStream_t s, int *nparts);
-int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, int count_word,
-                         const SortBufs &b, int cur,
-                         uint64_t *lbflags, uint32_t *ticket, uint32_t *state, const Tune &t,
-                         hipStream_t s, int *nparts);
+// Keys of the items in groups of more than kRunMax members (sa_build.hip's doubling rounds),
+// into b.keys[0]/b.vals[0] with their list indices in bigidx, fused with the histograms.
+int launch_big_extract(const uint32_t *P, const uint32_t *S, const uint32_t *rank, int64_t n,
+                       int rbits, int64_t a_bound, const SortBufs &b, uint32_t *bigidx,
+                       uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
+                       hipStream_t s, int *nparts);
+// The sorted large items to their indices in the round's full key/value list.
+int launch_big_place(const uint64_t *ks, const uint32_t *vs, const uint32_t *bigidx,
+                     int64_t a_bound, const uint32_t *state, uint64_t *K, uint32_t *V,
+                     uint32_t *err, hipStream_t s);
 
 }  // namespace saasm

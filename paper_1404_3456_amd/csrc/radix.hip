@@ -561,105 +561,165 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
     return SA_OK;
 }
 
-// Doubling-round keys, built in text order: for every position p whose group is not yet a
-// singleton, key = (rank[p] << rbits) | rank[p + h], value p, compacted in position order.
-// rank holds group labels (the suffix-array index of the group's first member) with kDone set
-// on singletons.  A suffix still in a non-singleton group after a round with prefix length h
-// has at least h symbols before its separator, so p + h stays inside the text.  The round's
-// active count and h are read from device memory (state[count_word], state[kStH]); the number
-// of keys written goes to state[kStKeys].  A count of 0 makes the launch a no-op (its zero
-// histograms are still written).
-constexpr int kKbBlock = 512;
-constexpr int kKbItems = 8;
-constexpr int kKbTile = kKbBlock * kKbItems;
+// Doubling-round keys of the items in large groups (more than kRunMax members), for the radix
+// passes of a round that also has small groups.  The previous rank update left the active items
+// in its sorted order: slots S[0..A) and positions P[0..A) with bit 31 on the first member of
+// each group, so a group is a run of consecutive items whose label is the slot of its first
+// member (a run's slots are consecutive).  An item belongs to a large group when its run is
+// longer than kRunMax: that is decided from the first-of-group bits of its own 64-item row and
+// the rows on either side.  For the j-th such item in order (tiles by ticket; the count of
+// large items and the last run start before each tile come from a look-back):
+//   keys[j] = (label << rbits) | rank[p + h],  vals[j] = p,  bigidx[j] = its index in the list,
+// with the label S[i] - (i - run start), and its digits added to the passes' histograms.  The
+// count goes to state[kStRadixN].  state[kStBig] == 0 (no large group) makes the launch write
+// zero histograms and a count of 0.  Persistent workgroups, one partial histogram each.
+constexpr int kBxBlock = 512;
+constexpr int kBxWaves = kBxBlock / kWave;
+constexpr int kBxRows = 64;                    // rows of 64 items per tile (one lane each in wave 0)
+constexpr int kBxK = kBxRows / kBxWaves;       // rows per wave
+constexpr int kBxTile = kBxRows * kWave;
 
 template <int D>
-__global__ __launch_bounds__(kKbBlock) void k_keys_dbl(const uint32_t *__restrict__ rank,
-                                                       uint32_t n, int rbits,
-                                                       uint64_t *__restrict__ keys,
-                                                       uint32_t *__restrict__ vals, int passes,
-                                                       uint32_t *__restrict__ hist,
-                                                       uint64_t *lbflags, uint32_t *tick,
-                                                       uint32_t *state, int count_word,
-                                                       uint32_t *err) {
+__global__ __launch_bounds__(kBxBlock) void k_big_extract(
+    const uint32_t *__restrict__ P, const uint32_t *__restrict__ S,
+    const uint32_t *__restrict__ rank, uint32_t n, int rbits, uint64_t *__restrict__ keys,
+    uint32_t *__restrict__ vals, uint32_t *__restrict__ bigidx, int passes,
+    uint32_t *__restrict__ hist, uint64_t *lbflags, uint32_t *tick, uint32_t *state,
+    uint32_t *err) {
     constexpr int R = 1 << D;
-    constexpr int W = kKbBlock / kWave;
     extern __shared__ uint32_t s_h[];
+    __shared__ uint64_t s_mask[kBxRows + 2];  // first-of-group bits per row; [0] and [kBxRows+1]: context
+    __shared__ uint32_t s_cnt[kBxRows];       // large items per row, then the exclusive count
+    __shared__ uint32_t s_last[kBxRows];      // last run start + 1 in the row, then before the row
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_chunk[kKbItems * W];
     __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const uint64_t rmask = (uint64_t(1) << rbits) - 1;
-    const uint32_t active = state[count_word];
+    const uint32_t A = state[kStBig] ? state[kStActive] : 0u;
     const uint32_t h = state[kStH];
-    const uint32_t ntiles = active ? (n + kKbTile - 1) / kKbTile : 0u;
-    for (int i = tid; i < passes * R; i += kKbBlock) s_h[i] = 0;
-    // Persistent: tiles are taken in ticket order until none is left, so every tile a
-    // look-back waits on belongs to a workgroup that is already running.
+    const uint32_t ntiles = (A + kBxTile - 1) / kBxTile;
+    const uint64_t rmask = (uint64_t(1) << rbits) - 1;
+    for (int i = tid; i < passes * R; i += kBxBlock) s_h[i] = 0;
+    if (A == 0 && blockIdx.x == 0 && tid == 0) state[kStRadixN] = 0;
     while (true) {
         __syncthreads();
         if (tid == 0) s_tile = ticket(tick);
         __syncthreads();
         const uint32_t tile = s_tile;
         if (tile >= ntiles) break;
-        const uint32_t tbase = tile * kKbTile;
-        uint32_t r[kKbItems];
+        const uint32_t tbase = tile * kBxTile;
+        uint32_t pv[kBxK];
 #pragma unroll
-        for (int j = 0; j < kKbItems; ++j) {
-            const uint32_t p = tbase + j * kKbBlock + tid;  // striped: a wave covers 64 in a row
-            r[j] = p < n ? rank[p] : kDone;
+        for (int k = 0; k < kBxK; ++k) {
+            const uint32_t row = k * kBxWaves + wave;
+            const uint32_t i = tbase + row * kWave + lane;
+            pv[k] = i < A ? P[i] : kDone;  // past the list: a group start
+            const uint64_t m = ballot((pv[k] & kDone) != 0);
+            if (lane == 0) s_mask[1 + row] = m;
         }
-#pragma unroll
-        for (int j = 0; j < kKbItems; ++j) {
-            const uint64_t act = ballot((r[j] & kDone) == 0);
-            if (lane == 0) s_chunk[j * W + wave] = uint32_t(popc64(act));
-        }
-        __syncthreads();
-        if (wave == 0) {
-            // chunks are ordered (j, wave); kKbItems * W <= 64 of them: one lane each
-            uint32_t c = lane < uint32_t(kKbItems * W) ? s_chunk[lane] : 0u;
-            uint32_t inc = wave_incl_scan<Sum32>(c);
-            uint32_t tile_total = __shfl(inc, kKbItems * W - 1);
-            if (lane < uint32_t(kKbItems * W)) s_chunk[lane] = inc - c;
-            uint64_t ex = lookback_tile<SumOp>(lbflags, int(tile), tile_total, err);
-            if (lane == 0) s_excl = ex;
-            if (lane == 0 && tile == ntiles - 1) state[kStKeys] = uint32_t(ex + tile_total);
+        if (wave < 2) {  // the rows before and after the tile
+            const int64_t i = wave == 0 ? int64_t(tbase) - kWave + lane : int64_t(tbase) + kBxTile + lane;
+            const uint32_t v = (i >= 0 && i < int64_t(A)) ? P[i] : kDone;
+            const uint64_t m = ballot((v & kDone) != 0);
+            if (lane == 0) s_mask[wave == 0 ? 0 : kBxRows + 1] = m;
         }
         __syncthreads();
+        const uint64_t le = lane == 63 ? ~uint64_t(0) : ((uint64_t(2) << lane) - 1);  // lanes <= lane
+        bool big[kBxK];
 #pragma unroll
-        for (int j = 0; j < kKbItems; ++j) {
-            const uint32_t p = tbase + j * kKbBlock + tid;
-            const uint64_t act = ballot((r[j] & kDone) == 0);
-            if ((r[j] & kDone) == 0) {
-                uint32_t r2 = 0;
-                if (p + h < n) r2 = rank[p + h] & kRankMask;
-                else raise_err(err, kErrRange);
-                const uint64_t k = ((uint64_t(r[j]) & rmask) << rbits) | (uint64_t(r2) & rmask);
-                const uint32_t o = uint32_t(s_excl) + s_chunk[j * W + wave] +
-                                   uint32_t(popc64(act & lanemask_lt()));
-                if (o < active) {
-                    keys[o] = k;
-                    vals[o] = p;
-                    hist_add<D>(s_h, k, passes);
-                } else {
-                    raise_err(err, kErrRange);
-                }
+        for (int k = 0; k < kBxK; ++k) {
+            const uint32_t row = k * kBxWaves + wave;
+            const uint32_t i = tbase + row * kWave + lane;
+            const uint64_t prev = s_mask[row], cur = s_mask[1 + row], next = s_mask[2 + row];
+            // distance back to the run start and forward to the next run start (capped)
+            uint32_t back = 2 * kWave, fwd = 2 * kWave;
+            const uint64_t mb = cur & le;
+            if (mb) back = lane - (63u - uint32_t(__clzll((long long)mb)));
+            else if (prev) back = lane + 1u + uint32_t(__clzll((long long)prev));
+            const uint64_t mf = cur & ~le;
+            if (mf) fwd = uint32_t(__ffsll((long long)mf)) - 1u - lane;
+            else if (next) fwd = kWave - lane + uint32_t(__ffsll((long long)next)) - 1u;
+            big[k] = i < A && back + fwd > uint32_t(kRunMax);
+            const uint64_t bb = ballot(big[k]);
+            if (lane == 0) {
+                s_cnt[row] = uint32_t(popc64(bb));
+                s_last[row] = cur ? tbase + row * kWave + (63u - uint32_t(__clzll((long long)cur))) + 1u : 0u;
             }
+        }
+        __syncthreads();
+        if (wave == 0) {  // rows in order, one lane each: (count, last start) scan, then the tiles
+            const uint64_t mine = (uint64_t(s_cnt[lane]) << 31) | s_last[lane];
+            const uint64_t inc = wave_incl_scan<CountLastOp>(mine);
+            uint64_t ex = __shfl_up(inc, 1);
+            if (lane == 0) ex = 0;
+            const uint64_t agg = __shfl(inc, kWave - 1);
+            const uint64_t before = lookback_tile<CountLastOp>(lbflags, int(tile), agg, err);
+            const uint64_t tot = CountLastOp::combine(before, ex);
+            s_cnt[lane] = uint32_t(tot >> 31);
+            s_last[lane] = uint32_t(tot & CountLastOp::kLastMask);
+            if (lane == 0 && tile == ntiles - 1)
+                state[kStRadixN] = uint32_t(CountLastOp::combine(before, agg) >> 31);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBxK; ++k) {
+            const uint32_t row = k * kBxWaves + wave;
+            const uint32_t i = tbase + row * kWave + lane;
+            const uint64_t bb = ballot(big[k]);
+            if (!big[k]) continue;
+            const uint64_t mb = s_mask[1 + row] & le;
+            const uint32_t start = mb ? tbase + row * kWave + (63u - uint32_t(__clzll((long long)mb)))
+                                      : s_last[row] - 1u;  // item 0 starts a run, so s_last >= 1
+            const uint32_t j = s_cnt[row] + uint32_t(popc64(bb & lanemask_lt()));
+            const uint32_t p = pv[k] & kRankMask;
+            const uint32_t sl = S[i];
+            if (start > i || sl < i - start || p >= n || h >= n - p || j >= A) {
+                raise_err(err, kErrRange);
+                continue;
+            }
+            const uint32_t label = sl - (i - start);
+            const uint32_t r2 = rank[p + h] & kRankMask;
+            const uint64_t key = ((uint64_t(label) & rmask) << rbits) | (uint64_t(r2) & rmask);
+            keys[j] = key;
+            vals[j] = p;
+            bigidx[j] = i;
+            hist_add<D>(s_h, key, passes);
         }
     }
     __syncthreads();
     hist_flush<D>(s_h, hist, passes);
 }
 
-int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, int count_word,
-                         const SortBufs &b, int cur, uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
-                         hipStream_t s, int *nparts) {
+// The large groups' items, sorted, to their places in the full list of the round: the j-th
+// sorted item goes to the j-th large item's index (both orders list the large groups in the
+// same order, each group's items contiguous).
+__global__ __launch_bounds__(256) void k_big_place(const uint64_t *__restrict__ ks,
+                                                   const uint32_t *__restrict__ vs,
+                                                   const uint32_t *__restrict__ bigidx,
+                                                   const uint32_t *state, uint64_t *__restrict__ K,
+                                                   uint32_t *__restrict__ V, uint32_t *err) {
+    const uint32_t B = state[kStRadixN], A = state[kStActive];
+    const uint32_t stride = gridDim.x * 256u;
+    for (uint32_t j = blockIdx.x * 256u + threadIdx.x; j < B; j += stride) {
+        const uint32_t t = bigidx[j];
+        if (t >= A) {
+            raise_err(err, kErrRange);
+            continue;
+        }
+        K[t] = ks[j];
+        V[t] = vs[j];
+    }
+}
+
+int launch_big_extract(const uint32_t *P, const uint32_t *S, const uint32_t *rank, int64_t n,
+                       int rbits, int64_t a_bound, const SortBufs &b, uint32_t *bigidx,
+                       uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
+                       hipStream_t s, int *nparts) {
     const int bits = 2 * rbits;
-    const int P = sort_passes(bits, t);
-    const int64_t tiles = (n + kKbTile - 1) / kKbTile;
+    const int P_ = sort_passes(bits, t);
+    const int64_t tiles = (a_bound + kBxTile - 1) / kBxTile;
     static int per_cu = 0;
     if (!per_cu) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_keys_dbl<8>, kKbBlock, size_t(P) * t.radix() * 4) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_big_extract<9>, kBxBlock, size_t(P_) * t.radix() * 4) != hipSuccess || per_cu < 1)
             per_cu = 1;
     }
     int64_t grid = int64_t(device_cus()) * per_cu;
@@ -667,18 +727,32 @@ int launch_keys_doubling(const uint32_t *rank, int64_t n, int rbits, int count_w
     if (grid > tiles) grid = tiles;
     if (grid < 1) grid = 1;
     *nparts = int(grid);
-    SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
+    SA_TRY(launch_fill_u64(lbflags, tiles > 0 ? tiles : 1, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
-    size_t lds = size_t(P) * t.radix() * 4;
-    // every position's label is read; each active one adds rank[p+h] and its key and value
-    TimedScope ts("keybuild", double(n) * 4.0, 16.0, s);
+    size_t lds = size_t(P_) * t.radix() * 4;
+    // per large item: position, slot and rank[p + h] read (12), key, value and index written (16)
+    TimedScope ts("keybuild", 0.0, 28.0, s);
     switch (t.dbits) {
-        case 4: hipLaunchKernelGGL(k_keys_dbl<4>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
-        case 8: hipLaunchKernelGGL(k_keys_dbl<8>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
-        case 9: hipLaunchKernelGGL(k_keys_dbl<9>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
-        case 11: hipLaunchKernelGGL(k_keys_dbl<11>, dim3(unsigned(grid)), dim3(kKbBlock), lds, s, rank, uint32_t(n), rbits, b.keys[cur], b.vals[cur], P, b.hist, lbflags, tick, state, count_word, b.err); break;
+        case 4: hipLaunchKernelGGL(k_big_extract<4>, dim3(unsigned(grid)), dim3(kBxBlock), lds, s, P, S, rank, uint32_t(n), rbits, b.keys[0], b.vals[0], bigidx, P_, b.hist, lbflags, tick, state, b.err); break;
+        case 8: hipLaunchKernelGGL(k_big_extract<8>, dim3(unsigned(grid)), dim3(kBxBlock), lds, s, P, S, rank, uint32_t(n), rbits, b.keys[0], b.vals[0], bigidx, P_, b.hist, lbflags, tick, state, b.err); break;
+        case 9: hipLaunchKernelGGL(k_big_extract<9>, dim3(unsigned(grid)), dim3(kBxBlock), lds, s, P, S, rank, uint32_t(n), rbits, b.keys[0], b.vals[0], bigidx, P_, b.hist, lbflags, tick, state, b.err); break;
+        case 11: hipLaunchKernelGGL(k_big_extract<11>, dim3(unsigned(grid)), dim3(kBxBlock), lds, s, P, S, rank, uint32_t(n), rbits, b.keys[0], b.vals[0], bigidx, P_, b.hist, lbflags, tick, state, b.err); break;
         default: return fail(SA_ERR_INVALID, "unsupported digit width");
     }
+    ts.finish();
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+int launch_big_place(const uint64_t *ks, const uint32_t *vs, const uint32_t *bigidx,
+                     int64_t a_bound, const uint32_t *state, uint64_t *K, uint32_t *V,
+                     uint32_t *err, hipStream_t s) {
+    int64_t g = (a_bound + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    // per large item: key, value and index read (16), key and value written (12)
+    TimedScope ts("big_place", 0.0, 28.0, s);
+    hipLaunchKernelGGL(k_big_place, dim3(unsigned(g)), dim3(256), 0, s, ks, vs, bigidx, state, K, V, err);
     ts.finish();
     SA_HIP(hipGetLastError());
     return SA_OK;

@@ -182,18 +182,16 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
 // Advances the round state after a rank update (one thread).
 __global__ void k_round_end(uint32_t *state, uint32_t h_first) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    state[kStBigLast] = state[kStRadixN];  // the round's large-group items (0 when none)
+    state[kStRadixN] = 0;
     if (state[kStActive] == 0) return;  // the round had nothing to do
     const uint32_t rounds = state[kStRounds];
     state[kStH] = rounds == 0 ? h_first : state[kStH] * 2u;
     state[kStRounds] = rounds + 1;
-    const uint32_t a = state[kStNext];
-    state[kStActive] = a;
-    // the next round sorts by radix passes only if a group is too large for the run sort
-    const uint32_t big = state[kStBigNext];
+    state[kStActive] = state[kStNext];
+    // the next round sorts the items of groups too large for the run sort by radix passes
+    state[kStBig] = state[kStBigNext];
     state[kStBigNext] = 0;
-    state[kStBig] = big;
-    state[kStRadixN] = big ? a : 0u;
-    state[kStRunsN] = big ? 0u : a;
 }
 
 // Adds a block's offset to suffix-array and inverse entries built for that block alone.
@@ -229,6 +227,7 @@ struct BuildLayout {
     uint32_t *rank;        // used when the caller gives no isa buffer
     uint32_t *slots[2];
     uint32_t *pos;         // active text positions in the last round's order (bit 31: run start)
+    uint32_t *bigidx;      // list index of each large-group item of a round (radix-sorted ones)
     SortBufs sb;
     uint64_t *lbflags;
     uint32_t *tickets;
@@ -247,6 +246,7 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
     L->slots[0] = c.take<uint32_t>(n);
     L->slots[1] = c.take<uint32_t>(n);
     L->pos = c.take<uint32_t>(n);
+    L->bigidx = c.take<uint32_t>(n);
     carve_sort(c, n, bits, t, &L->sb, true);
     const int64_t lbw = (n + kRuTile - 1) / kRuTile + (n + 2047) / 2048 + 16;
     L->lbflags = c.take<uint64_t>(lbw);
@@ -257,18 +257,19 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
     L->lcp_ws = n_sets > 0 ? c.take<char>(L->lcp_ws_bytes) : nullptr;
 }
 
-// Keys of a doubling round built in the previous round's sorted order, sorted group by group
-// without radix passes.  The previous rank update left the active items in that order: slots
-// S[0..A), text positions P[0..A) with bit 31 on the first member of each group, so each group
-// is a run of at most kRunMax items (the round runs this only when state[kStBig] is 0).  Its
-// label is the slot of the run's first member.  Item o gets
+// Keys of a doubling round built in the previous round's sorted order and sorted group by
+// group without radix passes.  The previous rank update left the active items in that order:
+// slots S[0..A) and text positions P[0..A) with bit 31 on the first member of each group, so
+// each group is a run whose label is the slot of its first member.  Item o of a run of at most
+// kRunMax items gets
 //   key = (label << rbits) | rank[p + h],
 // and goes to the run's first index plus the number of run members with a smaller key (equal
-// keys keep their order), which is where a stable sort of the whole array puts it.
-// Tiles of kKrTile items, loaded with kRunMax items of context on either side, so every run
-// that meets the tile lies inside the loaded range.  The active count and h come from
-// state[count_word] and state[kStH]; a count of 0 makes the launch a no-op.  A run longer
-// than kRunMax raises kErrRange.
+// keys keep their order), which is where a stable sort of the whole array puts it.  Items of
+// longer runs are left to the radix passes (k_big_extract, k_big_place) when state[kStBig] is
+// set, and raise kErrRange otherwise.  Tiles of kKrTile items, loaded with kRunMax items of
+// context on either side, so every run of at most kRunMax items that meets the tile lies inside
+// the loaded range.  The active count and h come from state[kStActive] and state[kStH]; a count
+// of 0 makes the launch a no-op.
 constexpr int kKrBlock = 256;
 constexpr int kKrTile = 2048;
 constexpr int kKrSpan = kKrTile + 2 * kRunMax;
@@ -276,12 +277,13 @@ constexpr int kKrSpan = kKrTile + 2 * kRunMax;
 __global__ __launch_bounds__(kKrBlock) void k_keys_runs(
     const uint32_t *__restrict__ P, const uint32_t *__restrict__ S,
     const uint32_t *__restrict__ rank, uint32_t n, int rbits, const uint32_t *state,
-    int count_word, uint64_t *__restrict__ K, uint32_t *__restrict__ V, uint32_t *err) {
+    uint64_t *__restrict__ K, uint32_t *__restrict__ V, uint32_t *err) {
     __shared__ uint32_t s_p[kKrSpan];   // position | first-of-run bit; outside [0, A): the bit alone
     __shared__ uint32_t s_r2[kKrSpan];  // rank[p + h]
     __shared__ uint32_t s_lab[kKrSpan]; // slot (the label, on a run's first member)
-    const uint32_t A = state[count_word];
+    const uint32_t A = state[kStActive];
     const uint32_t h = state[kStH];
+    const bool mixed = state[kStBig] != 0;  // longer runs exist and are sorted elsewhere
     const int64_t tbase = int64_t(blockIdx.x) * kKrTile;
     if (tbase >= int64_t(A)) return;
     const int64_t lo = tbase - kRunMax;
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(kKrBlock) void k_keys_runs(
         int en = li + 1;
         while (!(s_p[en] & kDone) && en - st < kRunMax) ++en;
         if (!(s_p[st] & kDone) || !(s_p[en] & kDone)) {
-            raise_err(err, kErrRange);  // a run longer than kRunMax: not this kernel's case
+            if (!mixed) raise_err(err, kErrRange);  // a run longer than kRunMax
             continue;
         }
         const uint32_t r2 = s_r2[li];
@@ -331,14 +333,13 @@ __global__ __launch_bounds__(kKrBlock) void k_keys_runs(
 
 static int launch_keys_runs(const uint32_t *P, const uint32_t *S, const uint32_t *rank,
                             int64_t a_bound, int64_t n, int rbits, const uint32_t *state,
-                            int count_word, uint64_t *K, uint32_t *V, uint32_t *err,
-                            hipStream_t s) {
+                            uint64_t *K, uint32_t *V, uint32_t *err, hipStream_t s) {
     int64_t tiles = (a_bound + kKrTile - 1) / kKrTile;
     if (tiles < 1) tiles = 1;
     // algorithmic bytes per item: read P, S and rank[p + h] (4 each); write K (8) and V (4)
     TimedScope ts("keyruns", 0.0, 24.0, s);
     hipLaunchKernelGGL(k_keys_runs, dim3(unsigned(tiles)), dim3(kKrBlock), 0, s, P, S, rank,
-                       uint32_t(n), rbits, state, count_word, K, V, err);
+                       uint32_t(n), rbits, state, K, V, err);
     ts.finish();
     SA_HIP(hipGetLastError());
     return SA_OK;
@@ -378,7 +379,7 @@ struct PinnedState {
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool ok = false;
     PinnedState() {
-        ok = hipHostMalloc(reinterpret_cast<void **>(&h), 64, hipHostMallocDefault) == hipSuccess &&
+        ok = hipHostMalloc(reinterpret_cast<void **>(&h), 2 * kStWords * 4, hipHostMallocDefault) == hipSuccess &&
              hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) == hipSuccess;
     }
@@ -403,15 +404,15 @@ struct Build {
     int key0_bits = 2 * kH0 + 5;
     int rbits = 1;
 
-    // copies the 8 state words to pinned slot k and records its event (stream order)
+    // copies the state words to pinned slot k and records its event (stream order)
     int snapshot(PinnedState &ps, int k) {
-        SA_HIP(hipMemcpyAsync(ps.h + 8 * k, L.state, 32, hipMemcpyDeviceToHost, s));
+        SA_HIP(hipMemcpyAsync(ps.h + kStWords * k, L.state, kStWords * 4, hipMemcpyDeviceToHost, s));
         SA_HIP(hipEventRecord(ps.ev[k], s));
         return SA_OK;
     }
 
-    int read_state(uint32_t host[8]) {
-        SA_HIP(hipMemcpyAsync(host, L.state, 32, hipMemcpyDeviceToHost, s));
+    int read_state(uint32_t host[kStWords]) {
+        SA_HIP(hipMemcpyAsync(host, L.state, kStWords * 4, hipMemcpyDeviceToHost, s));
         SA_HIP(hipStreamSynchronize(s));
         timing_flush();
         return SA_OK;
@@ -442,11 +443,13 @@ struct Build {
     }
 
     // One doubling round reading its slots from slots[sl] and writing slots[sl ^ 1]; a_bound
-    // bounds the active count (grid and fill sizes).  Unless runs_only, both sorts are
-    // enqueued and exactly one does work, chosen on the device (state[kStBig]); both leave the
-    // sorted keys in the buffer the passes end in.  runs_only enqueues the run sort alone,
-    // for rounds after one whose groups all had at most kRunMax members: groups only split,
-    // so that stays true (a longer run would raise kErrRange).
+    // bounds the active count (grid and fill sizes).  Groups of at most kRunMax members are
+    // sorted run by run in LDS (k_keys_runs).  Unless runs_only, the items of larger groups,
+    // if the device state says there are any (state[kStBig]), are taken out with their keys,
+    // sorted by radix passes and put back in their groups' places; every kernel of that part
+    // reads its count from device memory and does nothing when it is 0.  runs_only leaves
+    // that part out, for rounds after one whose groups all had at most kRunMax members: groups
+    // only split, so that stays true (a longer run would raise kErrRange).
     int doubling_round(int sl, int64_t a_bound, bool runs_only = false) {
         int cur = 0;
         if (!runs_only) {
@@ -454,16 +457,24 @@ struct Build {
             SA_TRY(sort_prepare(L.sb, a_bound, bits, t, s));
             int nparts = 0;
             timing_scope_mode(kModeRadix);
-            SA_TRY(launch_keys_doubling(rank, n, rbits, kStRadixN, L.sb, 0, L.lbflags, L.tickets, L.state, t, s, &nparts));
+            SA_TRY(launch_big_extract(L.pos, L.slots[sl], rank, n, rbits, a_bound, L.sb, L.bigidx,
+                                      L.lbflags, L.tickets, L.state, t, s, &nparts));
             SA_TRY(sort_run(L.sb, 0, L.state + kStRadixN, a_bound, 0, bits, t, nparts, s, &cur));
         }
+        // the round's full list goes to the buffer the passes did not end in
+        uint64_t *K = L.sb.keys[cur ^ 1];
+        uint32_t *V = L.sb.vals[cur ^ 1];
         timing_scope_mode(kModeRuns);
-        SA_TRY(launch_keys_runs(L.pos, L.slots[sl], rank, a_bound, n, rbits, L.state,
-                                runs_only ? kStActive : kStRunsN, L.sb.keys[cur], L.sb.vals[cur],
+        SA_TRY(launch_keys_runs(L.pos, L.slots[sl], rank, a_bound, n, rbits, L.state, K, V,
                                 L.state + kStErr, s));
+        if (!runs_only) {
+            timing_scope_mode(kModeRadix);
+            SA_TRY(launch_big_place(L.sb.keys[cur], L.sb.vals[cur], L.bigidx, a_bound, L.state, K, V,
+                                    L.state + kStErr, s));
+        }
         timing_scope_mode(kModeAny);
-        SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], L.slots[sl], a_bound, n, false, h0,
-                                  rbits, sa, rank, L.slots[sl ^ 1], L.pos, L.lbflags, L.tickets, L.state, s));
+        SA_TRY(launch_rank_update(K, V, L.slots[sl], a_bound, n, false, h0, rbits, sa, rank,
+                                  L.slots[sl ^ 1], L.pos, L.lbflags, L.tickets, L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
@@ -472,7 +483,7 @@ struct Build {
     int run(bool use_graph, int *rounds_out) {
         rbits = bits_for(n - 1);
         SA_TRY(round0());
-        uint32_t host[8];
+        uint32_t host[kStWords];
         if (use_graph) {
             SA_TRY(read_state(host));
             SA_TRY(check_err(host[kStErr]));
@@ -537,7 +548,10 @@ struct Build {
             // Round 1 waits for round 0's state: if its groups are all small, no round needs
             // the radix passes again.
             SA_HIP(hipEventSynchronize(ps.ev[cur]));
-            bool runs_only = ps.h[8 * cur + kStBig] == 0;
+            bool runs_only = ps.h[kStWords * cur + kStBig] == 0;
+            // A round's units of work are known one round late: its active count from the
+            // state before it, its large-group item count from the state after it.
+            int64_t prev_tag = -1, prev_active = 0;
             for (int guard = 0;; ++guard) {
                 if (guard > 40) return fail(SA_ERR_HIP, "sa_build: doubling did not converge");
                 const int64_t tag = timing_round_begin();
@@ -545,9 +559,10 @@ struct Build {
                 SA_TRY(snapshot(ps, cur ^ 1));
                 sl ^= 1;
                 SA_HIP(hipEventSynchronize(ps.ev[cur]));
-                memcpy(host, ps.h + 8 * cur, sizeof(uint32_t) * 8);
-                // the state before the round just enqueued holds that round's active count
-                timing_round_items(tag, host[kStActive], host[kStBig] ? kModeRadix : kModeRuns);
+                memcpy(host, ps.h + kStWords * cur, sizeof(uint32_t) * kStWords);
+                if (prev_tag >= 0) timing_round_items(prev_tag, prev_active, host[kStBigLast]);
+                prev_tag = tag;
+                prev_active = host[kStActive];  // the state before the round just enqueued
                 timing_poll();
                 SA_TRY(check_err(host[kStErr]));
                 if (host[kStBig] == 0) runs_only = true;
@@ -555,7 +570,8 @@ struct Build {
                 if (host[kStActive] == 0) {
                     // the round just enqueued is a no-op; wait for it so the stream is clean
                     SA_HIP(hipEventSynchronize(ps.ev[cur]));
-                    memcpy(host, ps.h + 8 * cur, sizeof(uint32_t) * 8);
+                    memcpy(host, ps.h + kStWords * cur, sizeof(uint32_t) * kStWords);
+                    timing_round_items(prev_tag, 0, 0);
                     timing_flush();
                     SA_TRY(check_err(host[kStErr]));
                     break;
