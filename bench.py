@@ -154,7 +154,7 @@ def bench_batched(args, pkg, torch, np):
     if args.autotune:
         from paper_1404_3456_amd import autotune
         tuning, tune_report = autotune.autotune(
-            text, off, candidates=[(8, 512, 16), (9, 512, 16), (9, 256, 16), (11, 512, 16)],
+            text, off, candidates=[(9, 1024, 16), (8, 1024, 16), (9, 512, 16), (11, 512, 16)],
             seg_packs=(0, 1 << 28), reps=1, use_cache=False, log=log)
         log(f"autotuned: {tuning}")
 
@@ -163,8 +163,9 @@ def bench_batched(args, pkg, torch, np):
         plain_tuning = pkg.Tuning(tuning.digit_bits, tuning.block_threads, tuning.items_per_thread, 0)
 
     def batched():
-        sa, isa = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=args.graph)
-        lcp = pkg.sa_lcp(text, sa, isa)
+        # the batched build computes the LCP array itself (its scan keeps to each set's block)
+        sa, isa, lcp = pkg.sa_build_batched(text, off, tuning=tuning, use_graph=args.graph,
+                                            lcp=True)
         ovl = pkg.sa_overlaps(text, sa, isa, lcp, min_len)
         return sa, ovl
 
@@ -192,6 +193,12 @@ def bench_batched(args, pkg, torch, np):
 
     tb, (sa_b, ovl_b) = timed(batched, args.steps)
     log(f"batched: {tb*1e3:.1f} ms")
+    pkg.sa_timing_reset()
+    pkg.sa_timing_enable(True)
+    batched()
+    torch.cuda.synchronize()
+    pkg.sa_timing_enable(False)
+    kern = kernel_table(pkg, KEYS + ("big_place",), 1)
     tp, outs = timed(plain, max(1, args.steps // 2))
     log(f"plain per set: {tp*1e3:.1f} ms")
     # the batched result must equal the per-set plain result (overlap rows per set)
@@ -214,6 +221,7 @@ def bench_batched(args, pkg, torch, np):
         "batched_Msuffixes_per_s": round(cat.size / tb / 1e6, 1),
         "overlap_rows": int(ovl_b.shape[0]),
         "rows_match_plain": bool(same),
+        "kernels": kern,
         "autotune": tune_report,
     }
     print(json.dumps(out), flush=True)
@@ -508,7 +516,7 @@ SURVEY_BYTES = {
     "pack": 1.375,        # read the byte, write 2 code bits and the separator bit
     "key0": 8.25,         # write an 8-byte first-round key from the 2-bit codes
     "radix_pass": 24.0,   # read and write an 8-byte key and a 4-byte value
-    "keybuild": 20.0,     # doubling keys, per active suffix
+    "keybuild": 20.0,     # doubling keys, per large-group item (read rank[p+h]; write key, value)
     "keyruns": 20.0,      # the same keys, built and ordered run by run
     "rank_update": 16.0,  # read key 8 + SA 4, write the rank 4, per active suffix
     "kasai": 12.0,        # isa 4 + the gathered sa 4 + the lcp write 4, per suffix
@@ -519,7 +527,7 @@ KERNEL_NAMES = {
     "rank_update": "k_rank_update (group labels; random 4-byte scatter)",
     "kasai": "k_kasai (LCP; random gathers)",
     "keyruns": "k_keys_runs (doubling keys sorted group by group in LDS)",
-    "keybuild": "k_keys_dbl (doubling keys in text order)",
+    "keybuild": "k_big_extract (doubling keys of the large groups' items)",
     "key0": "k_key0 (first-round keys + digit histograms)",
     "overlap_walk": "k_ovl_walk (LCP-interval walks)",
 }

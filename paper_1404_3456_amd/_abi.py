@@ -274,12 +274,13 @@ def sa_build_batched_ws_bytes(n: int, n_sets: int, tuning=None, set_off=None) ->
     return int(load().sa_build_batched_ws_bytes(n, n_sets, ptr, _tune(tuning)))
 
 
-def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bool = True,
+def sa_build_batched(text, set_off, isa: bool = True, tuning=None, use_graph: bool = False,
                      stream=None, return_rounds: bool = False, lcp: bool = False):
     """Suffix arrays of many texts laid end to end.  `set_off` (host, int64, n_sets+1) bounds
     text s as text[set_off[s]:set_off[s+1]].  Returns (sa, isa) in concatenated coordinates:
     sa[set_off[s]:set_off[s+1]] is the suffix array of text s; with lcp=True, (sa, isa, lcp)
-    where lcp is computed inside the same call (its status is checked)."""
+    where lcp is computed inside the same call (its status is checked).  use_graph replays the
+    doubling rounds from a captured hipGraph instead of the host-driven loop (same result)."""
     import numpy as np
     torch = _torch()
     lib = load()

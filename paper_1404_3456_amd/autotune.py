@@ -72,7 +72,7 @@ def autotune(text, set_off=None, candidates=None, seg_packs=(0,), reps=2, cache_
                 if set_off is None:
                     _abi.sa_build(text, isa=True, tuning=tu)
                 else:
-                    _abi.sa_build_batched(text, set_off, isa=True, tuning=tu)
+                    _abi.sa_build_batched(text, set_off, isa=True, tuning=tu, use_graph=False)
 
             run()
             torch.cuda.synchronize()

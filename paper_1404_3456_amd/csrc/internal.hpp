@@ -129,10 +129,13 @@ int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 int launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 
 // LCP array (Kasai's scan; lcp.hip): workspace bytes and the body of sa_lcp.  A failure found
-// on the device is written to flag[0] (default: lcp[0]) as the negative status.
+// on the device is written to flag[0] (default: lcp[0]) as the negative status.  `span` bounds
+// the range of suffix-array indices and text positions one text's accesses fall in (a batch of
+// texts: its largest text; 0: n); it chooses between the two forms of the scan.
 int64_t lcp_ws_bytes(int64_t n);
 int lcp_run(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa, int32_t *lcp,
-            void *ws, int64_t ws_bytes, hipStream_t stream, int32_t *flag = nullptr);
+            void *ws, int64_t ws_bytes, hipStream_t stream, int32_t *flag = nullptr,
+            int64_t span = 0);
 
 // radix sort plumbing
 struct SortBufs {

@@ -134,7 +134,7 @@ int64_t lcp_ws_bytes(int64_t n) {
 }
 
 int lcp_run(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa, int32_t *lcp,
-            void *ws, int64_t ws_bytes, hipStream_t stream, int32_t *flag) {
+            void *ws, int64_t ws_bytes, hipStream_t stream, int32_t *flag, int64_t span) {
     if (ws_bytes < lcp_ws_bytes(n)) return fail(SA_ERR_NOMEM, "sa_lcp: workspace too small");
     Carver c(ws, ws_bytes);
     uint32_t *packed = c.take<uint32_t>(packed_words(n));
@@ -142,7 +142,9 @@ int lcp_run(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *is
     uint32_t *wordcnt = c.take<uint32_t>(sepmask_words(n));
     uint4 *blk = c.take<uint4>(sepmask_words(n));
     uint32_t *err = c.take<uint32_t>(64);
-    const bool plcp = n >= g_plcp_min_n;
+    // the scattered writes of one text stay inside its own block of the array: with texts of
+    // a batch below the threshold the direct form keeps its locality however large the batch
+    const bool plcp = (span > 0 && span < n ? span : n) >= g_plcp_min_n;
     int32_t *pl = plcp ? c.take<int32_t>(n) : nullptr;
     SA_TRY(launch_fill_u32(err, 1, 0, stream));
     SA_TRY(launch_pack(text, n, packed, sepmask, wordcnt, err, stream));

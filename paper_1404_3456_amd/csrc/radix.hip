@@ -575,9 +575,11 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
 // zero histograms and a count of 0.  Persistent workgroups, one partial histogram each.
 constexpr int kBxBlock = 512;
 constexpr int kBxWaves = kBxBlock / kWave;
-constexpr int kBxRows = 64;                    // rows of 64 items per tile (one lane each in wave 0)
+constexpr int kBxRows = 256;                   // rows of 64 items per tile
 constexpr int kBxK = kBxRows / kBxWaves;       // rows per wave
+constexpr int kBxLoad = 8;                     // rows whose loads a wave keeps in flight
 constexpr int kBxTile = kBxRows * kWave;
+constexpr int kBxPer = kBxRows / kWave;        // rows per lane in the row scan
 
 template <int D>
 __global__ __launch_bounds__(kBxBlock) void k_big_extract(
@@ -589,15 +591,16 @@ __global__ __launch_bounds__(kBxBlock) void k_big_extract(
     constexpr int R = 1 << D;
     extern __shared__ uint32_t s_h[];
     __shared__ uint64_t s_mask[kBxRows + 2];  // first-of-group bits per row; [0] and [kBxRows+1]: context
-    __shared__ uint32_t s_cnt[kBxRows];       // large items per row, then the exclusive count
+    __shared__ uint64_t s_bigm[kBxRows];      // large-group items per row
+    __shared__ uint32_t s_cnt[kBxRows];       // their count, then the exclusive count
     __shared__ uint32_t s_last[kBxRows];      // last run start + 1 in the row, then before the row
     __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t A = state[kStBig] ? state[kStActive] : 0u;
     const uint32_t h = state[kStH];
     const uint32_t ntiles = (A + kBxTile - 1) / kBxTile;
     const uint64_t rmask = (uint64_t(1) << rbits) - 1;
+    const uint64_t le = lane == 63 ? ~uint64_t(0) : ((uint64_t(2) << lane) - 1);  // lanes <= lane
     for (int i = tid; i < passes * R; i += kBxBlock) s_h[i] = 0;
     if (A == 0 && blockIdx.x == 0 && tid == 0) state[kStRadixN] = 0;
     while (true) {
@@ -607,14 +610,19 @@ __global__ __launch_bounds__(kBxBlock) void k_big_extract(
         const uint32_t tile = s_tile;
         if (tile >= ntiles) break;
         const uint32_t tbase = tile * kBxTile;
-        uint32_t pv[kBxK];
+        // 1. first-of-group masks of the tile's rows (a streaming read of the positions)
+        for (int k0 = 0; k0 < kBxK; k0 += kBxLoad) {
+            uint32_t pv[kBxLoad];
 #pragma unroll
-        for (int k = 0; k < kBxK; ++k) {
-            const uint32_t row = k * kBxWaves + wave;
-            const uint32_t i = tbase + row * kWave + lane;
-            pv[k] = i < A ? P[i] : kDone;  // past the list: a group start
-            const uint64_t m = ballot((pv[k] & kDone) != 0);
-            if (lane == 0) s_mask[1 + row] = m;
+            for (int k = 0; k < kBxLoad; ++k) {
+                const uint32_t i = tbase + ((k0 + k) * kBxWaves + wave) * kWave + lane;
+                pv[k] = i < A ? P[i] : kDone;  // past the list: a group start
+            }
+#pragma unroll
+            for (int k = 0; k < kBxLoad; ++k) {
+                const uint64_t m = ballot((pv[k] & kDone) != 0);
+                if (lane == 0) s_mask[1 + (k0 + k) * kBxWaves + wave] = m;
+            }
         }
         if (wave < 2) {  // the rows before and after the tile
             const int64_t i = wave == 0 ? int64_t(tbase) - kWave + lane : int64_t(tbase) + kBxTile + lane;
@@ -623,14 +631,12 @@ __global__ __launch_bounds__(kBxBlock) void k_big_extract(
             if (lane == 0) s_mask[wave == 0 ? 0 : kBxRows + 1] = m;
         }
         __syncthreads();
-        const uint64_t le = lane == 63 ? ~uint64_t(0) : ((uint64_t(2) << lane) - 1);  // lanes <= lane
-        bool big[kBxK];
-#pragma unroll
+        // 2. which items lie in runs longer than kRunMax: the distance back to the run start
+        //    and forward to the next one (capped), from the row and its neighbours
         for (int k = 0; k < kBxK; ++k) {
             const uint32_t row = k * kBxWaves + wave;
             const uint32_t i = tbase + row * kWave + lane;
             const uint64_t prev = s_mask[row], cur = s_mask[1 + row], next = s_mask[2 + row];
-            // distance back to the run start and forward to the next run start (capped)
             uint32_t back = 2 * kWave, fwd = 2 * kWave;
             const uint64_t mb = cur & le;
             if (mb) back = lane - (63u - uint32_t(__clzll((long long)mb)));
@@ -638,39 +644,51 @@ __global__ __launch_bounds__(kBxBlock) void k_big_extract(
             const uint64_t mf = cur & ~le;
             if (mf) fwd = uint32_t(__ffsll((long long)mf)) - 1u - lane;
             else if (next) fwd = kWave - lane + uint32_t(__ffsll((long long)next)) - 1u;
-            big[k] = i < A && back + fwd > uint32_t(kRunMax);
-            const uint64_t bb = ballot(big[k]);
+            const uint64_t bb = ballot(i < A && back + fwd > uint32_t(kRunMax));
             if (lane == 0) {
+                s_bigm[row] = bb;
                 s_cnt[row] = uint32_t(popc64(bb));
                 s_last[row] = cur ? tbase + row * kWave + (63u - uint32_t(__clzll((long long)cur))) + 1u : 0u;
             }
         }
         __syncthreads();
-        if (wave == 0) {  // rows in order, one lane each: (count, last start) scan, then the tiles
-            const uint64_t mine = (uint64_t(s_cnt[lane]) << 31) | s_last[lane];
-            const uint64_t inc = wave_incl_scan<CountLastOp>(mine);
+        if (wave == 0) {  // rows in order, kBxPer per lane: (count, last start) scan, then the tiles
+            uint64_t v[kBxPer];
+            uint64_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kBxPer; ++q) {
+                const uint32_t row = lane * kBxPer + q;
+                v[q] = run;  // exclusive within the lane's rows
+                run = CountLastOp::combine(run, (uint64_t(s_cnt[row]) << 31) | s_last[row]);
+            }
+            const uint64_t inc = wave_incl_scan<CountLastOp>(run);
             uint64_t ex = __shfl_up(inc, 1);
             if (lane == 0) ex = 0;
             const uint64_t agg = __shfl(inc, kWave - 1);
-            const uint64_t before = lookback_tile<CountLastOp>(lbflags, int(tile), agg, err);
-            const uint64_t tot = CountLastOp::combine(before, ex);
-            s_cnt[lane] = uint32_t(tot >> 31);
-            s_last[lane] = uint32_t(tot & CountLastOp::kLastMask);
+            const uint64_t before = CountLastOp::combine(
+                lookback_tile<CountLastOp>(lbflags, int(tile), agg, err), ex);
+#pragma unroll
+            for (int q = 0; q < kBxPer; ++q) {
+                const uint32_t row = lane * kBxPer + q;
+                const uint64_t tot = CountLastOp::combine(before, v[q]);
+                s_cnt[row] = uint32_t(tot >> 31);
+                s_last[row] = uint32_t(tot & CountLastOp::kLastMask);
+            }
             if (lane == 0 && tile == ntiles - 1)
-                state[kStRadixN] = uint32_t(CountLastOp::combine(before, agg) >> 31);
+                state[kStRadixN] = uint32_t(CountLastOp::combine(before, agg) >> 31);  // lane 0: ex = 0
         }
         __syncthreads();
-#pragma unroll
+        // 3. keys of the large-group items (rows without any are skipped)
         for (int k = 0; k < kBxK; ++k) {
             const uint32_t row = k * kBxWaves + wave;
+            const uint64_t bb = s_bigm[row];
+            if (!bb || !((bb >> lane) & 1u)) continue;
             const uint32_t i = tbase + row * kWave + lane;
-            const uint64_t bb = ballot(big[k]);
-            if (!big[k]) continue;
             const uint64_t mb = s_mask[1 + row] & le;
             const uint32_t start = mb ? tbase + row * kWave + (63u - uint32_t(__clzll((long long)mb)))
                                       : s_last[row] - 1u;  // item 0 starts a run, so s_last >= 1
             const uint32_t j = s_cnt[row] + uint32_t(popc64(bb & lanemask_lt()));
-            const uint32_t p = pv[k] & kRankMask;
+            const uint32_t p = P[i] & kRankMask;
             const uint32_t sl = S[i];
             if (start > i || sl < i - start || p >= n || h >= n - p || j >= A) {
                 raise_err(err, kErrRange);

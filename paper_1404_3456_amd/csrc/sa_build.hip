@@ -623,8 +623,11 @@ static int build_common(const uint8_t *text, int64_t n, const int64_t *set_off_h
     }
     if (lcp_or_null) {
         if (n_sets < 1 || !B.L.lcp_ws) return fail(SA_ERR_INVALID, "LCP output needs a batched build");
+        int64_t span = 0;  // the largest text of the batch
+        for (int32_t k = 0; k < n_sets; ++k)
+            span = set_off_h[k + 1] - set_off_h[k] > span ? set_off_h[k + 1] - set_off_h[k] : span;
         SA_TRY(lcp_run(text, n, sa, reinterpret_cast<const int32_t *>(B.rank), lcp_or_null,
-                       B.L.lcp_ws, B.L.lcp_ws_bytes, stream, lcp_flag));
+                       B.L.lcp_ws, B.L.lcp_ws_bytes, stream, lcp_flag, span));
     }
     if (rounds_h) *rounds_h = rounds;
     return SA_OK;

@@ -556,6 +556,53 @@ def test_build_switches_from_radix_rounds_to_run_sort(lib, seed):
     assert runs_bytes > 0, "no doubling round sorted group by group"
 
 
+def mixed_groups_text(seed):
+    """Error-free reads of a random genome at ~10x (groups of about ten members after the first
+    round, all small) plus 60 copies of one 600-base tandem read ((AC)^150 then (AGT)^100) and
+    40 reads cut from a long run of a 7-base unit: the repeat suffixes stay in groups of 40 to
+    several hundred members through every round, beside the many small groups."""
+    rng = np.random.default_rng([synth.SEED_BASE, 701, seed])
+    genome = rng.choice(np.frombuffer(b"ACGT", dtype=np.uint8), 30_000).tobytes().decode()
+    reads = []
+    for _ in range(1200):
+        s0 = int(rng.integers(0, len(genome) - 250))
+        reads.append(genome[s0:s0 + 250])
+    tandem = "AC" * 150 + "AGT" * 100
+    reads += [tandem] * 60
+    unit = "".join(rng.choice(list("ACGT"), 7))
+    long_run = unit * 400
+    for _ in range(40):
+        s0 = int(rng.integers(0, 7 * 300))
+        reads.append(long_run[s0:s0 + 500])
+    order = rng.permutation(len(reads))
+    return synth.text_from_strings([reads[k] for k in order])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_mixed_group_sizes_every_round(lib, seed):
+    """Rounds with groups of more than 32 members beside many of at most 32: the small ones are
+    sorted run by run, only the large groups' items go through the radix passes, and the build
+    equals the oracle (SA, LCP, overlaps).  The timing records show both sorts working in the
+    doubling rounds, over fewer radix items than active items."""
+    text = mixed_groups_text(seed)
+    n = text.size
+    lib.sa_timing_reset()
+    lib.sa_timing_enable(True)
+    try:
+        sa, isa, lcp, ovl = run_all(lib, text, 30)
+    finally:
+        lib.sa_timing_enable(False)
+    want = oracle.suffix_array(text)
+    assert np.array_equal(sa, want)
+    assert np.array_equal(isa[want], np.arange(n))
+    assert np.array_equal(lcp, oracle.lcp_array(text, want))
+    assert np.array_equal(ovl, oracle.overlaps(text, 30))
+    big_items = lib.sa_timing_items("keybuild")     # large-group items taken out, all rounds
+    run_items = lib.sa_timing_items("keyruns")      # active items of the same rounds
+    assert big_items > 0, "no large group reached the radix passes"
+    assert run_items > big_items, "the small groups were not sorted run by run"
+
+
 # ---- the weighted overlap graph's maximal path over GPU-built overlaps (Sec. III) ------------
 
 @pytest.mark.parametrize("seed", range(4))
