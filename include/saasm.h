@@ -193,6 +193,18 @@ int64_t sa_lcp_ws_bytes(int64_t n);
 int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
            int32_t *lcp, void *ws, int64_t ws_bytes, hipStream_t stream);
 
+/* sa_lcp_noalloc: sa_lcp for callers that cannot allocate (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, result and error
+ * reporting as sa_lcp, but no workspace argument: the scratch is one array of 18 MiB that the
+ * library holds in every GPU's memory until the process ends, so 1 <= n <= 2^24
+ * (sa_lcp_noalloc_max_n(); larger n: SA_ERR_TOO_LARGE).  Allocates nothing (no device, pinned
+ * or host memory on success, no timing events).  Every call on one GPU uses that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other host threads) race, so the
+ * caller orders them; one stream orders them by itself. */
+int64_t sa_lcp_noalloc_max_n(void);
+int sa_lcp_noalloc(const uint8_t *text, int64_t n, const int32_t *sa, const int32_t *isa,
+                   int32_t *lcp, hipStream_t stream);
+
 /* sa_lcp_status: synchronises `stream` and returns the status an earlier sa_lcp (or
  * sa_build_batched with an LCP output) on that stream left in lcp[0]: SA_OK when it is 0. */
 int sa_lcp_status(const int32_t *lcp, hipStream_t stream);

@@ -91,6 +91,8 @@ def load():
         "sa_strand_rows": ([P, I64, I64, P, I64, P, P, I64, P], ctypes.c_int),
         "sa_lookup": ([P, I64, P, P, P, I64, ctypes.c_int32, P, P, I64, P], ctypes.c_int),
         "sa_lcp": ([P, I64, P, P, P, P, I64, P], ctypes.c_int),
+        "sa_lcp_noalloc": ([P, I64, P, P, P, P], ctypes.c_int),
+        "sa_lcp_noalloc_max_n": ([], I64),
         "sa_lcp_set_chunk": ([I32], ctypes.c_int),
         "sa_lcp_plcp_min": ([I64], I64),
         "sa_overlaps_ws_bytes": ([I64, I64, I64], I64),
@@ -321,6 +323,21 @@ def sa_lcp(text, sa, isa, stream=None, check: bool = False):
     if check:
         sa_lcp_status(lcp, stream)
     return lcp
+
+
+def sa_lcp_noalloc(text, sa, isa, lcp, stream=None, check: bool = False):
+    """sa_lcp into the caller's `lcp` tensor with the library's own device scratch (no
+    allocation; n <= sa_lcp_noalloc_max_n())."""
+    lib = load()
+    t = _dev_text(text)
+    _check(lib.sa_lcp_noalloc(_ptr(t), t.numel(), _ptr(sa), _ptr(isa), _ptr(lcp), _stream(stream)))
+    if check:
+        sa_lcp_status(lcp, stream)
+    return lcp
+
+
+def sa_lcp_noalloc_max_n() -> int:
+    return int(load().sa_lcp_noalloc_max_n())
 
 
 def sa_lcp_status(lcp, stream=None):

@@ -13,6 +13,9 @@
 // and then gather LCP[i] = PLCP[SA[i]]: once the arrays exceed the last-level cache a random
 // 4-byte gather costs about half of a random 4-byte scatter (measured 46 vs 25 G/s over 1.6 GB),
 // while below it the scatter is the cheaper of the two.
+#include <mutex>
+#include <string>
+
 #include "device.hpp"
 #include "internal.hpp"
 #include "text.hpp"
@@ -191,6 +194,52 @@ extern "C" int sa_lcp(const uint8_t *text, int64_t n, const int32_t *sa, const i
     if (n < 1) return fail(SA_ERR_INVALID, "sa_lcp: n must be >= 1");
     if (n >= kMaxN) return fail(SA_ERR_TOO_LARGE, "sa_lcp: n >= 2^31-2");
     return lcp_run(text, n, sa, isa, lcp, ws, ws_bytes, stream);
+}
+
+// ---- the LCP array without allocation ----------------------------------------------------
+// For callers that cannot allocate (code under stream capture, tight serving loops): the
+// workspace is one file-scope device array, which every GPU the library runs on holds until
+// the process ends.  Host code never passes the array's name to a kernel (that is a host-side
+// stand-in); the device address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+namespace saasm {
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 24;  // characters
+constexpr int64_t kNoAllocBytes = int64_t(18) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace saasm
+
+static __device__ __align__(256) uint8_t scratch[saasm::kNoAllocBytes];
+
+namespace saasm {
+static std::once_flag g_scratch_once[kMaxDevices];
+static void *g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_rc[kMaxDevices];
+}  // namespace saasm
+
+extern "C" int64_t sa_lcp_noalloc_max_n(void) { return kNoAllocMaxN; }
+
+extern "C" int sa_lcp_noalloc(const uint8_t *text, int64_t n, const int32_t *sa,
+                              const int32_t *isa, int32_t *lcp, hipStream_t stream) {
+    if (!text || !sa || !isa || !lcp) return fail(SA_ERR_INVALID, "sa_lcp_noalloc: NULL pointer");
+    if (n < 1) return fail(SA_ERR_INVALID, "sa_lcp_noalloc: n must be >= 1");
+    if (n > kNoAllocMaxN)
+        return fail(SA_ERR_TOO_LARGE, "sa_lcp_noalloc: n above its scratch limit of 2^24 characters");
+    const int64_t need = lcp_ws_bytes(n);
+    if (need > kNoAllocBytes) return fail(SA_ERR_NOMEM, "sa_lcp_noalloc: scratch too small");
+    int dev = 0;
+    SA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SA_ERR_INVALID, "sa_lcp_noalloc: device index");
+    std::call_once(g_scratch_once[dev], [dev] {
+        g_scratch_rc[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+    });
+    if (g_scratch_rc[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return fail(SA_ERR_HIP, std::string("sa_lcp_noalloc: hipGetSymbolAddress: ") +
+                                    hipGetErrorString(g_scratch_rc[dev]));
+    // no timing events either: creating them may allocate
+    timing_pause(true);
+    const int rc = lcp_run(text, n, sa, isa, lcp, g_scratch_ptr[dev], need, stream);
+    timing_pause(false);
+    return rc;
 }
 
 // Waits for the stream and reports the status sa_lcp left in lcp[0].
