@@ -333,16 +333,34 @@ def serving_measure(args, pkg, np, texts):
     log(f"served saturated: {sat_s}")
     bound_ms = args.p99_bound_ms
     points = []
-    for k in (1.0, 2.0, 3.0, 3.5, 4.0, 4.5, 5.0, 6.0):
+
+    def point(k):
+        """Served run at k x the plain capacity; True when it kept up within the p99 bound."""
         rate = k * mu_p
         if rate > 1.1 * sat_s["completed_jobs_per_s"]:
-            break
+            return False
         pt = run(0, rate, jobs_at(rate), args.workers)
-        pt["rate_x_plain"] = k
+        pt["rate_x_plain"] = round(k, 4)
         points.append(pt)
-        log(f"served {k}x: {pt}")
-        if not (pt["kept_up"] and pt["p99_ms"] <= bound_ms) and k >= 2.0:
+        log(f"served {k:.3f}x: {pt}")
+        return pt["kept_up"] and pt["p99_ms"] <= bound_ms
+
+    # whole multiples of the plain capacity until one is not kept up, then three halvings of
+    # the interval between the last rate kept up and the first one that was not
+    lo = hi = None
+    for k in (1.0, 2.0, 3.0, 4.0, 5.0, 6.0):
+        if point(k):
+            lo = k
+        else:
+            hi = k
             break
+    if lo is not None and hi is not None:
+        for _ in range(3):
+            mid = 0.5 * (lo + hi)
+            if point(mid):
+                lo = mid
+            else:
+                hi = mid
     ok = [p for p in points if p["kept_up"] and p["p99_ms"] <= bound_ms]
     best = max(ok, key=lambda p: p["completed_jobs_per_s"]) if ok else None
     return {
