@@ -44,7 +44,7 @@ R guard(F &&body) noexcept {
     } while (0)
 
 constexpr int64_t kMaxN = (int64_t(1) << 31) - 2;  // n <= kMaxN - 1: labels fit in 31 bits
-constexpr uint32_t kDone = 1u << 31;      // rank word flag: suffix's group is a singleton
+constexpr uint32_t kDone = 1u << 31;      // bit 31 flag: first member of a group (positions), singleton (rank update)
 constexpr uint32_t kRankMask = kDone - 1;
 constexpr int kH0 = 29;                   // bases in the first-round key (58 code bits + 5)
 

@@ -40,7 +40,7 @@ constexpr int kRuTile = kRuBlock * kRuItems;
 //               the suffix ended at its separator, which no other suffix shares);
 //   single(i) = head(i) and head(i+1) (i+1 == A counts as a head);
 //   label(i)  = S[g] where g is the last head at or before i.
-// Writes rank[V[i]] = label | (single ? kDone : 0), sa[S[i]] = V[i] once item i is a singleton
+// Writes rank[V[i]] = label, sa[S[i]] = V[i] once item i is a singleton
 // (its slot is then final; nothing reads the slots of suffixes still in a group), and the slots
 // of items that are not singletons, compacted in order, to S_new; their count to
 // state[kStNext].
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
         if (slot >= n || v >= n) continue;  // reported above
         const uint32_t lw = s_lab[i];
         if (lw != kNone) {
-            rank[v] = lw;
+            rank[v] = lw & kRankMask;  // bit 31 only marks a singleton here
             if (lw & kDone) sa[slot] = int32_t(v);  // final; slots still in a group are rewritten later
         }
         const uint32_t o = s_out[i];
@@ -201,11 +201,6 @@ __global__ __launch_bounds__(256) void k_add_offset(int32_t *__restrict__ sa, in
     if (i >= n) return;
     sa[i] += base;
     if (isa) isa[i] += base;
-}
-
-__global__ __launch_bounds__(256) void k_strip(uint32_t *__restrict__ rank, uint32_t n) {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) rank[i] &= kRankMask;
 }
 
 // Every text of a batch must be non-empty and end with a separator.
@@ -616,11 +611,6 @@ static int build_common(const uint8_t *text, int64_t n, const int64_t *set_off_h
     }
     int rounds = 0;
     SA_TRY(B.run(use_graph, &rounds));
-    if (isa_or_null || lcp_or_null) {
-        unsigned grid = unsigned((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-        hipLaunchKernelGGL(k_strip, dim3(grid), dim3(256), 0, stream, B.rank, uint32_t(n));
-        SA_HIP(hipGetLastError());
-    }
     if (lcp_or_null) {
         if (n_sets < 1 || !B.L.lcp_ws) return fail(SA_ERR_INVALID, "LCP output needs a batched build");
         int64_t span = 0;  // the largest text of the batch
