@@ -734,9 +734,13 @@ def main():
     avg_s = ms * 1e-3 / L
     per_unit = SURVEY_BYTES.get(dom)
     alg = items / L * per_unit if per_unit is not None else by / L
+    traffic = traffic_for(args, dom, tuning)
     roofline = {"bound": "hbm", "achieved": round(alg / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for(args, dom, tuning),
+                "traffic": traffic,
+                # the counted bytes over the same launch time: how busy the memory side is
+                "traffic_GBs": round(traffic / avg_s / 1e9, 1) if traffic else None,
+                "traffic_frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "kernel": KERNEL_NAMES[dom],
                 "units_per_launch": round(items / L),
                 "bytes_per_unit": per_unit,
