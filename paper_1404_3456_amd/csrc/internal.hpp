@@ -186,8 +186,8 @@ int launch_key0(const uint32_t *packed, const uint32_t *sepmask, int64_t n, int 
 // into b.keys[0]/b.vals[0] with their list indices in bigidx, fused with the histograms.
 int launch_big_extract(const uint32_t *P, const uint32_t *S, const uint32_t *rank, int64_t n,
                        int rbits, int64_t a_bound, const SortBufs &b, uint32_t *bigidx,
-                       uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
-                       hipStream_t s, int *nparts);
+                       uint64_t *lbflags, int64_t lb_words, uint32_t *tick, uint32_t *state,
+                       const Tune &t, hipStream_t s, int *nparts);
 // The sorted large items to their indices in the round's full key/value list.
 int launch_big_place(const uint64_t *ks, const uint32_t *vs, const uint32_t *bigidx,
                      int64_t a_bound, const uint32_t *state, uint64_t *K, uint32_t *V,

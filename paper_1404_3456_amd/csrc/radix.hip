@@ -730,11 +730,12 @@ __global__ __launch_bounds__(256) void k_big_place(const uint64_t *__restrict__ 
 
 int launch_big_extract(const uint32_t *P, const uint32_t *S, const uint32_t *rank, int64_t n,
                        int rbits, int64_t a_bound, const SortBufs &b, uint32_t *bigidx,
-                       uint64_t *lbflags, uint32_t *tick, uint32_t *state, const Tune &t,
-                       hipStream_t s, int *nparts) {
+                       uint64_t *lbflags, int64_t lb_words, uint32_t *tick, uint32_t *state,
+                       const Tune &t, hipStream_t s, int *nparts) {
     const int bits = 2 * rbits;
     const int P_ = sort_passes(bits, t);
     const int64_t tiles = (a_bound + kBxTile - 1) / kBxTile;
+    if (tiles > lb_words) return fail(SA_ERR_HIP, "large-group extraction: look-back array too small");
     static int per_cu = 0;
     if (!per_cu) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_big_extract<9>, kBxBlock, size_t(P_) * t.radix() * 4) != hipSuccess || per_cu < 1)

@@ -33,6 +33,10 @@ namespace saasm {
 constexpr int kRuBlock = 1024;
 constexpr int kRuItems = 8;
 constexpr int kRuTile = kRuBlock * kRuItems;
+// Smallest tile of a kernel that takes the build's tile look-back words (the rank update; the
+// large-group extraction's tiles are larger): the array holds one word per tile of this size,
+// and every launcher checks its tile count against that on the host.
+constexpr int kLbMinTile = kRuTile;
 
 // Rank update over the sorted active items (K, V) of a round, whose suffix-array slots are
 // S[0..A) (S == nullptr: identity, round 0).  For item i:
@@ -225,6 +229,7 @@ struct BuildLayout {
     uint32_t *bigidx;      // list index of each large-group item of a round (radix-sorted ones)
     SortBufs sb;
     uint64_t *lbflags;
+    int64_t lb_words;      // look-back words in lbflags
     uint32_t *tickets;
     uint32_t *state;       // kSt* words
     int64_t *set_off;      // batched builds: [n_sets + 1]
@@ -243,8 +248,8 @@ static void carve_build(Carver &c, int64_t n, int n_sets, const Tune &t, BuildLa
     L->pos = c.take<uint32_t>(n);
     L->bigidx = c.take<uint32_t>(n);
     carve_sort(c, n, bits, t, &L->sb, true);
-    const int64_t lbw = (n + kRuTile - 1) / kRuTile + (n + 2047) / 2048 + 16;
-    L->lbflags = c.take<uint64_t>(lbw);
+    L->lb_words = (n + kLbMinTile - 1) / kLbMinTile + 16;
+    L->lbflags = c.take<uint64_t>(L->lb_words);
     L->tickets = c.take<uint32_t>(64);
     L->state = c.take<uint32_t>(64);
     L->set_off = c.take<int64_t>(n_sets + 1);
@@ -343,9 +348,11 @@ static int launch_keys_runs(const uint32_t *P, const uint32_t *S, const uint32_t
 static int launch_rank_update(const uint64_t *K, const uint32_t *V, const uint32_t *S,
                               int64_t a_bound, int64_t n, bool round0, int h0, int rbits,
                               int32_t *sa, uint32_t *rank, uint32_t *S_new, uint32_t *P_new,
-                              uint64_t *lbflags, uint32_t *tick, uint32_t *state, hipStream_t s) {
+                              uint64_t *lbflags, int64_t lb_words, uint32_t *tick,
+                              uint32_t *state, hipStream_t s) {
     int64_t tiles = (a_bound + kRuTile - 1) / kRuTile;
     if (tiles < 1) tiles = 1;
+    if (tiles > lb_words) return fail(SA_ERR_HIP, "rank update: look-back array too small");
     SA_TRY(launch_fill_u64(lbflags, tiles, 0, s));
     SA_TRY(launch_fill_u32(tick, 1, 0, s));
     // algorithmic bytes: read K (8) + V (4) + S (4 when present); write sa (4) + rank (4) +
@@ -431,7 +438,8 @@ struct Build {
         int cur = 0;
         SA_TRY(sort_run(L.sb, 0, nullptr, n, 0, key0_bits, t, nparts, s, &cur));
         SA_TRY(launch_rank_update(L.sb.keys[cur], L.sb.vals[cur], nullptr, n, n, true, h0, rbits,
-                                  sa, rank, L.slots[0], L.pos, L.lbflags, L.tickets, L.state, s));
+                                  sa, rank, L.slots[0], L.pos, L.lbflags, L.lb_words, L.tickets,
+                                  L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
@@ -453,7 +461,7 @@ struct Build {
             int nparts = 0;
             timing_scope_mode(kModeRadix);
             SA_TRY(launch_big_extract(L.pos, L.slots[sl], rank, n, rbits, a_bound, L.sb, L.bigidx,
-                                      L.lbflags, L.tickets, L.state, t, s, &nparts));
+                                      L.lbflags, L.lb_words, L.tickets, L.state, t, s, &nparts));
             SA_TRY(sort_run(L.sb, 0, L.state + kStRadixN, a_bound, 0, bits, t, nparts, s, &cur));
         }
         // the round's full list goes to the buffer the passes did not end in
@@ -469,7 +477,8 @@ struct Build {
         }
         timing_scope_mode(kModeAny);
         SA_TRY(launch_rank_update(K, V, L.slots[sl], a_bound, n, false, h0, rbits, sa, rank,
-                                  L.slots[sl ^ 1], L.pos, L.lbflags, L.tickets, L.state, s));
+                                  L.slots[sl ^ 1], L.pos, L.lbflags, L.lb_words, L.tickets,
+                                  L.state, s));
         hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, L.state, uint32_t(h0));
         SA_HIP(hipGetLastError());
         return SA_OK;
