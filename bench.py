@@ -578,6 +578,7 @@ def traffic_for(args, key, tuning):
     only for the sources the counters were taken on and the default tuning."""
     import hashlib
     sources = {"radix_pass": ("radix.hip", "device.hpp"),
+               "sa_build": ("sa_build.hip", "radix.hip", "pack.hip", "device.hpp", "internal.hpp"),
                "rank_update": ("sa_build.hip", "device.hpp", "internal.hpp"),
                "kasai": ("lcp.hip", "text.hpp", "device.hpp", "internal.hpp"),
                "keyruns": ("sa_build.hip", "device.hpp", "internal.hpp")}
@@ -701,8 +702,13 @@ def main():
     build_kern = kernel_table(pkg, BUILD_KEYS, ks)
     b8 = sum(e.get("survey_bytes_per_step", 0) for e in build_kern.values())
     bimpl = sum(e["impl_bytes_per_step"] for e in build_kern.values())
+    # the build's counted traffic (all its kernels, one build) where it was taken on these sources
+    btr = traffic_for(args, "sa_build", tuning)
     sa_build = {
         "ms": round(sa_build_ms, 3),
+        "traffic": btr,
+        "traffic_GBs": round(btr / (sa_build_ms * 1e-3) / 1e9, 1) if btr else None,
+        "traffic_frac": round(btr / (sa_build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if btr else None,
         "Msuffixes_per_s": round(n / (sa_build_ms * 1e-3) / 1e6, 3),
         "survey_bytes": b8,
         "achieved_GBs": round(b8 / (sa_build_ms * 1e-3) / 1e9, 1),
@@ -714,7 +720,8 @@ def main():
         "kernels": build_kern,
         "note": "bytes = units of work x bytes per unit, by the survey's per-kernel figures "
                 "(survey_*) and by the implementation's own model (impl_*), over the build's "
-                "time with no instrumentation",
+                "time with no instrumentation; traffic = FETCH_SIZE + WRITE_SIZE of every kernel "
+                "of one build, counted at the L2 boundary (profiles/sa_build_traffic.json)",
     }
     log(f"SA build alone: {sa_build_ms:.3f} ms, {sa_build['frac']:.3f} of peak (survey bytes)")
 
