@@ -507,12 +507,49 @@ def test_overlaps_rc_vs_oracle(lib, case):
         assert np.array_equal(got, oracle.overlaps_rc(text, ml)), (case, text.size)
 
 
+def _rc_rows_of(reads, a, min_len):
+    """Every row with read a first, from the three-orientation definition written out with
+    prefix hashing of its own (no suffix array and none of the oracle's code): for each way the
+    reads can meet, the longest l >= min_len with the last l bases of A equal to the first l of
+    B, found by looking up each suffix start of A among the min_len-base prefixes of B."""
+    comp = bytes.maketrans(b"ACGT", b"TGCA")
+
+    def rc(x):
+        return x.translate(comp)[::-1]
+
+    pref = [{}, {}]  # strand-0/2 B is a read, strand-1 B is a read's reverse complement
+    for b, x in enumerate(reads):
+        if len(x) >= min_len:
+            pref[0].setdefault(x[:min_len], []).append(b)
+            pref[1].setdefault(rc(x)[:min_len], []).append(b)
+    rows = {}
+    for o, A, table, flip in ((0, reads[a], pref[0], False), (1, reads[a], pref[1], True),
+                              (2, rc(reads[a]), pref[0], False)):
+        for start in range(0, len(A) - min_len + 1):
+            l = len(A) - start
+            for b in table.get(A[start:start + min_len], ()):
+                if b == a:
+                    continue
+                B = rc(reads[b]) if flip else reads[b]
+                if l <= len(B) and A[start:] == B[:l] and (b, o) not in rows:
+                    rows[(b, o)] = l  # start ascending: the first match is the longest
+    return sorted([a, b, o, l] for (b, o), l in rows.items())
+
+
 def test_overlaps_rc_sampled_large(lib):
-    """A 10 M-character sample of the plain large workload (doubled to 20 M)."""
+    """A 10 M-character sample of the plain large workload (doubled to 20 M): all rows against
+    the oracle, and the rows of 30 sampled reads against the three-orientation definition
+    checked directly (independent of the doubled-text reduction both sides use)."""
     r = synth.large_plain(scale=0.2)
     got = lib.sa_overlaps_rc(dev(r.text), r.min_len).cpu().numpy()
     want = oracle.overlaps_rc(r.text, r.min_len)
     assert got.shape[0] > 1000 and np.array_equal(got, want)
+    reads = bytes(r.text).split(b"$")[:-1]
+    rng = np.random.default_rng(17)
+    for a in sorted(rng.choice(len(reads), size=30, replace=False)):
+        lo, hi = np.searchsorted(got[:, 0], [a, a + 1])
+        mine = got[lo:hi].tolist()
+        assert mine == _rc_rows_of(reads, int(a), r.min_len), f"read {a}"
 
 
 def stem_family_text(seed):
