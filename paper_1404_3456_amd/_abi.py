@@ -62,6 +62,11 @@ def load():
         return _lib
     if not os.path.exists(_LIB):
         raise ImportError(f"{_LIB} is missing: build it with `python -m paper_1404_3456_amd.build`")
+    # torch first: its bundled HIP runtime carries the soname the library links against, so the
+    # library binds to that one copy.  Opened before torch, the library would pull the system
+    # runtime in beside torch's, and tensors, streams and the server's threads would then be
+    # split over two HIP (and two HSA) runtimes in one process.
+    _torch()
     lib = ctypes.CDLL(_LIB)
     P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     TP = ctypes.POINTER(_Tuning)

@@ -136,6 +136,29 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         _abi.load()
 
 
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before anything imports torch still leaves one HIP runtime and one
+    HSA runtime mapped in the process once torch is in use (a fresh interpreter, no GPU needed:
+    the mapped files are read from /proc/self/maps)."""
+    import subprocess
+    import sys
+    code = ("from paper_1404_3456_amd import _abi\n"
+            "_abi.load()\n"
+            "import torch\n"
+            "torch.zeros(1)\n"
+            "libs = set()\n"
+            "for line in open('/proc/self/maps'):\n"
+            "    f = line.split()[-1]\n"
+            "    if 'libamdhip64' in f or 'libhsa-runtime64' in f:\n"
+            "        libs.add(os.path.realpath(f))\n"
+            "print(len([f for f in libs if 'amdhip' in f]), len([f for f in libs if 'hsa' in f]))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", "import os\n" + code], cwd=root,
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split()[-2:] == ["1", "1"], out.stdout
+
+
 def test_one_workspace_covers_the_path():
     """sa_workspace_bytes is at least what each call of the path asks for: sa_build (default
     tuning), sa_lcp (both LCP forms) and sa_overlaps with up to n candidate matches."""
