@@ -73,7 +73,7 @@ def parse():
                          "jobs/6 per second run 6 s of arrivals)")
     ap.add_argument("--keep-up", type=float, default=0.98,
                     help="serving: a rate counts only if completed >= this x offered")
-    ap.add_argument("--workers", type=int, default=4, help="serving: server worker streams")
+    ap.add_argument("--workers", type=int, default=8, help="serving: server worker streams")
     ap.add_argument("--max-jobs", type=int, default=64, help="serving: jobs per batch at most")
     ap.add_argument("--p99-bound-ms", type=float, default=500.0, help="serving: p99 bound")
     ap.add_argument("--patterns", type=int, default=1_000_000, help="lookup: patterns per step")

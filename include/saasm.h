@@ -377,7 +377,10 @@ typedef struct {
  * own to overlap with it, so each worker owns one (non-blocking, default priority).  Callers
  * order their own work after a job through asm_poll, which reports a job done only once its
  * results are complete in device memory.
- * Admission: queued jobs are laid into a batch while their memory fits.  When a batch of
+ * Admission: queued jobs are laid into a batch in arrival order, up to max_jobs_per_batch jobs
+ * and 2^30 characters, all with the min_len of the first; up to 16 queued jobs that do not
+ * match (another min_len, or past the character limit) are passed over and keep their place.
+ * The batch is admitted while its memory fits.  When a batch of
  * several jobs does not fit, half as many are tried at once (the full batch size returns with
  * the next admission that fits).  A single job that does not fit waits until a batch ends or
  * the caller releases a finished job (asm_release); it fails with SA_ERR_NOMEM only when it

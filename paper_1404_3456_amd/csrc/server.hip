@@ -358,13 +358,14 @@ static void worker_main(asm_server *S) {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
             if (S->stop && S->queue.empty()) break;
-            // admission: FIFO with bounded look-ahead, one min_len per batch
+            // admission: FIFO, one min_len per batch; at most `lookahead` queued jobs that do
+            // not fit this batch (another min_len, or past the character limit) are passed over
             int64_t chars = 0;
-            int looked = 0;
-            for (auto it = S->queue.begin(); it != S->queue.end() && looked < S->lookahead;) {
+            int skipped = 0;
+            for (auto it = S->queue.begin(); it != S->queue.end() && skipped < S->lookahead;) {
                 Job *j = *it;
-                ++looked;
                 if (!js.empty() && (j->min_len != js[0]->min_len || chars + j->n > S->max_chars)) {
+                    ++skipped;
                     ++it;
                     continue;
                 }

@@ -233,3 +233,33 @@ def test_batching_resumes_after_a_job_too_large_to_share(pkg):
         assert np.array_equal(sa, want)
         assert np.array_equal(lcp, oracle.lcp_array(t, want))
         assert np.array_equal(ovl, oracle.overlaps(t, 40))
+
+
+def test_batches_fill_to_the_batch_size(pkg):
+    """A 20 M-character job keeps the one worker busy while 40 small jobs queue behind it; with
+    batches of up to 64 jobs the small ones are admitted together, so the whole run takes at
+    most two batches (a cap below the batch size, e.g. 16 jobs, would need three or more)."""
+    huge = synth.genome_reads(931, 2_000_000, 40_000, 500, err=0.005)
+    smalls = [synth.genome_reads(940 + k, 20_000, 200, 250, err=0.005) for k in range(40)]
+    with pkg.AsmServer(4 << 30, max_jobs_per_batch=64, workers=1) as srv:
+        ids = [srv.asm_submit(huge, 40, borrow=True)]
+        ids += [srv.asm_submit(t, 40, borrow=True) for t in smalls]
+        got = []
+        for jid in ids:
+            r = wait(srv, jid, timeout=300.0)
+            assert r["status"] == 0
+            got.append(host(r))
+            srv.asm_release(jid)
+        st = srv.asm_server_stats()
+    assert st["jobs_done"] == 41 and st["arena_used"] == 0
+    assert st["batches"] <= 2, st
+    for (sa, isa, lcp, ovl), t in zip(got[1:], smalls):
+        want = oracle.suffix_array(t)
+        assert np.array_equal(sa, want)
+        assert np.array_equal(lcp, oracle.lcp_array(t, want))
+        assert np.array_equal(ovl, oracle.overlaps(t, 40))
+    sa, isa, lcp, ovl = got[0]
+    assert np.array_equal(isa[sa], np.arange(huge.size))
+    bad, first = oracle.check_all(huge, sa, lcp)
+    assert bad == 0, (bad, first)
+    assert np.array_equal(ovl, oracle.overlaps(huge, 40))
