@@ -600,7 +600,7 @@ def traffic_for(args, key, tuning):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                           "(the design for more GPUs is described, not run)"}))
         sys.exit(2)
     import numpy as np
