@@ -597,6 +597,36 @@ def traffic_for(args, key, tuning):
     return tr.get("bytes_per_launch")
 
 
+def copy_ceiling(pkg, torch, dev, reps=10):
+    """The practical bandwidth ceiling: a 1 GiB device-to-device copy (1 GiB read + 1 GiB
+    written per copy), timed with events on the stream the copies run on, by the runtime's own
+    copy (torch `copy_`, hipMemcpyAsync device to device) and by the library's plain
+    grid-stride copy kernel (the one the traffic counters are scaled by)."""
+    words = 256 << 20
+    src = torch.ones(words, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    moved = 2 * 4 * words
+    out = {"bytes_per_copy": moved}
+    for name, fn in (("runtime_copy", lambda: dst.copy_(src)),
+                     ("k_copy_u32", lambda: pkg.sa_copy_u32(dst, src))):
+        for _ in range(3):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        out[name + "_GBs"] = round(moved / sec / 1e9, 1)
+    out["GBs"] = max(out["runtime_copy_GBs"], out["k_copy_u32_GBs"])
+    out["frac_of_peak"] = round(out["GBs"] / HBM_PEAK_GBS, 4)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -758,6 +788,12 @@ def main():
                 "impl_frac": round(by / L / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"dominant kernel {dom}: {d}")
 
+    copy = copy_ceiling(pkg, torch, dev)
+    log(f"copy ceiling: {copy}")
+    if sa_build.get("traffic_GBs"):
+        sa_build["traffic_vs_copy"] = round(sa_build["traffic_GBs"] / copy["GBs"], 4)
+    sa_build["survey_vs_copy"] = round(sa_build["achieved_GBs"] / copy["GBs"], 4)
+
     served = None
     if serving_texts is not None:
         log("served-jobs leg ...")
@@ -792,6 +828,7 @@ def main():
         "sa_build": sa_build,
         "kernels": kern,
         "roofline": roofline,
+        "copy_ceiling": copy,
         "served": served,
         "cpu_baseline": cpu,
     }
