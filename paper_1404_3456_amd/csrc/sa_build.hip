@@ -77,14 +77,42 @@ __global__ __launch_bounds__(kRuBlock) void k_rank_update(
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
     const uint32_t tbase = tile * kRuTile;
-    for (uint32_t i = tid; i < uint32_t(kRuTile); i += kRuBlock) {
-        const bool in = tbase + i < A;
-        s_k[1 + i] = in ? K[tbase + i] : 0;
-        s_s[i] = in ? (S ? S[tbase + i] : tbase + i) : 0;
-        s_v[i] = in ? V[tbase + i] : 0;
+    {
+        // Every load of the thread is issued before the first LDS store (indices past the
+        // active count read the last item and are then dropped), so the tile costs one memory
+        // latency rather than one per item and array.
+        uint64_t kr[kRuItems];
+        uint32_t sr[kRuItems], vr[kRuItems];
+#pragma unroll
+        for (int j = 0; j < kRuItems; ++j) {
+            const uint32_t i = tbase + tid + uint32_t(j) * kRuBlock;
+            const uint32_t c = i < A ? i : A - 1;  // A >= 1: this tile holds an item
+            kr[j] = K[c];
+            vr[j] = V[c];
+        }
+        if (S) {
+#pragma unroll
+            for (int j = 0; j < kRuItems; ++j) {
+                const uint32_t i = tbase + tid + uint32_t(j) * kRuBlock;
+                sr[j] = S[i < A ? i : A - 1];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kRuItems; ++j) sr[j] = tbase + tid + uint32_t(j) * kRuBlock;
+        }
+        const uint64_t kprev = (tid == 0 && tbase > 0) ? K[tbase - 1] : 0;
+        const uint64_t knext = (tid == 1 && tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
+#pragma unroll
+        for (int j = 0; j < kRuItems; ++j) {
+            const uint32_t li = tid + uint32_t(j) * kRuBlock;
+            const bool in = tbase + li < A;
+            s_k[1 + li] = in ? kr[j] : 0;
+            s_s[li] = in ? sr[j] : 0;
+            s_v[li] = in ? vr[j] : 0;
+        }
+        if (tid == 0) s_k[0] = kprev;
+        if (tid == 1) s_k[kRuTile + 1] = knext;
     }
-    if (tid == 0) s_k[0] = tbase > 0 ? K[tbase - 1] : 0;
-    if (tid == 1) s_k[kRuTile + 1] = (tbase + kRuTile < A) ? K[tbase + kRuTile] : 0;
     __syncthreads();
 
     const uint32_t first = tid * kRuItems;  // blocked: items first .. first+kRuItems-1
