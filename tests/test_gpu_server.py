@@ -263,3 +263,24 @@ def test_batches_fill_to_the_batch_size(pkg):
     bad, first = oracle.check_all(huge, sa, lcp)
     assert bad == 0, (bad, first)
     assert np.array_equal(ovl, oracle.overlaps(huge, 40))
+
+
+def test_mixed_min_len_jobs(pkg):
+    """Jobs with two minimum overlap lengths interleaved in the queue: a batch holds one length
+    and passes over (at most 16) queued jobs of the other, which keep their place; every job's
+    SA, LCP and overlaps (at its own length) equal the oracle's."""
+    texts = jobs_pool(30, seed=41)
+    lens = [20 if (k % 3) else 35 for k in range(len(texts))]
+    with pkg.AsmServer(1 << 30, max_jobs_per_batch=64, workers=2) as srv:
+        ids = [srv.asm_submit(t, L, borrow=True) for t, L in zip(texts, lens)]
+        for jid, t, L in zip(ids, texts, lens):
+            r = wait(srv, jid)
+            assert r["status"] == 0
+            sa, isa, lcp, ovl = host(r)
+            want = oracle.suffix_array(t)
+            assert np.array_equal(sa, want)
+            assert np.array_equal(lcp, oracle.lcp_array(t, want))
+            assert np.array_equal(ovl, oracle.overlaps(t, L)), (jid, L)
+            srv.asm_release(jid)
+        st = srv.asm_server_stats()
+    assert st["jobs_done"] == len(texts) and st["arena_used"] == 0
