@@ -180,6 +180,26 @@ def test_ragged_random(lib, seed, m, lo, hi, alpha):
     assert_parity(lib, t, min_len=4, label=f"seed{seed}")
 
 
+def text_of_length(seed, n):
+    """Overlapping reads of a random genome (8x), cut to exactly n characters ending in '$'."""
+    t = synth.genome_reads(seed, max(200, n // 8), max(4, n // 60), 60, err=0.01)
+    while t.size < n:
+        t = np.concatenate([t, synth.genome_reads(seed + t.size, max(200, n // 8), max(4, n // 60), 60)])
+    t = t[:n].copy()
+    t[-1] = ord("$")
+    return t
+
+
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 8191, 8192, 8193, 16383, 16384, 16385, 24577])
+def test_lengths_at_tile_boundaries(lib, n):
+    """Texts whose length sits on either side of the tile sizes of the run sort (2,048 items), the
+    rank update (8,192) and the radix pass (16,384): round 0 has all n suffixes active, so its
+    last tile is full, a single item, or one short."""
+    t = text_of_length(n, n)
+    assert t.size == n and t[-1] == ord("$")
+    assert_parity(lib, t, min_len=10, label=f"n={n}")
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_overlapping_reads(lib, seed):
     t = synth.genome_reads(seed, 3000 + 1000 * seed, 300, 80 + 20 * seed, err=0.01 * (seed % 2),
